@@ -1,0 +1,186 @@
+"""CPU oracle for the homotopic alternating sequential filter (test infrastructure).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg may import this package. It wraps ``hasf_oracle.c`` (plain C, one thread),
+which shares nothing with the HIP library.
+
+All arrays are numpy uint8 images (nonzero = object) or uint32 distance maps,
+C-contiguous, shape (H, W).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hasf_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+U8P = ctypes.POINTER(ctypes.c_uint8)
+U32P = ctypes.POINTER(ctypes.c_uint32)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no threads)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    lib.oracle_simple_lut.argtypes = [ctypes.c_int, U8P]
+    lib.oracle_topo_numbers.argtypes = [ctypes.c_int, ctypes.c_uint,
+                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    for name in ("oracle_edt_sq", "oracle_edt_sq_direct"):
+        f = getattr(lib, name)
+        f.argtypes = [U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int, U32P]
+        f.restype = ctypes.c_int
+    for name in ("oracle_thin_p", "oracle_thicken_p", "oracle_thin_queue_p", "oracle_thicken_queue_p"):
+        f = getattr(lib, name)
+        f.argtypes = [U8P, U8P, U32P, ctypes.c_int, ctypes.c_int]
+        f.restype = ctypes.c_long
+    lib.oracle_thin_p_lut.argtypes = [U8P, U8P, U32P, ctypes.c_int, ctypes.c_int, U8P]
+    lib.oracle_thin_p_lut.restype = ctypes.c_long
+    for name in ("oracle_homotopic_thin", "oracle_homotopic_thicken"):
+        f = getattr(lib, name)
+        f.argtypes = [U8P, U8P, ctypes.c_int, ctypes.c_int]
+        f.restype = ctypes.c_long
+    lib.oracle_hc.argtypes = [U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.oracle_hc.restype = ctypes.c_long
+    lib.oracle_hf.argtypes = [U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.oracle_hf.restype = ctypes.c_long
+    lib.oracle_hasf.argtypes = [U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int, U8P]
+    lib.oracle_hasf.restype = ctypes.c_long
+    lib.oracle_hasf_queue.argtypes = [U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.oracle_hasf_queue.restype = ctypes.c_long
+    _lib = lib
+    return lib
+
+
+def _u8(a):
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    return a, a.ctypes.data_as(U8P)
+
+
+def _opt_u8(a):
+    if a is None:
+        return None, None
+    return _u8(a)
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise RuntimeError("%s failed with code %d" % (what, rc))
+    return rc
+
+
+def simple_lut(n: int = 8) -> np.ndarray:
+    """256-entry table: 1 where the neighbourhood code is simple for (n, n-bar)."""
+    lut = np.zeros(256, dtype=np.uint8)
+    _check(_load().oracle_simple_lut(n, lut.ctypes.data_as(U8P)), "simple_lut")
+    return lut
+
+
+def topo_numbers(n: int, m: int):
+    T = ctypes.c_int()
+    Tb = ctypes.c_int()
+    _check(_load().oracle_topo_numbers(n, m, ctypes.byref(T), ctypes.byref(Tb)), "topo_numbers")
+    return T.value, Tb.value
+
+
+def edt_sq(feat, frame: bool = False, direct: bool = False) -> np.ndarray:
+    """Squared Euclidean distance to the nearest nonzero pixel (+ outside if frame)."""
+    f, fp = _u8(feat)
+    H, W = f.shape
+    out = np.zeros((H, W), dtype=np.uint32)
+    fn = _load().oracle_edt_sq_direct if direct else _load().oracle_edt_sq
+    _check(fn(fp, H, W, int(bool(frame)), out.ctypes.data_as(U32P)), "edt_sq")
+    return out
+
+
+def thin_p(S, K, P, queue: bool = False):
+    s, sp = _u8(S)
+    s = s.copy()
+    sp = s.ctypes.data_as(U8P)
+    k, kp = _opt_u8(K)
+    p = np.ascontiguousarray(P, dtype=np.uint32)
+    fn = _load().oracle_thin_queue_p if queue else _load().oracle_thin_p
+    rounds = _check(fn(sp, kp, p.ctypes.data_as(U32P), s.shape[0], s.shape[1]), "thin")
+    return s, rounds
+
+
+def thin_p_lut(S, K, P, lut):
+    s = np.ascontiguousarray(S, dtype=np.uint8).copy()
+    k, kp = _opt_u8(K)
+    p = np.ascontiguousarray(P, dtype=np.uint32)
+    l = np.ascontiguousarray(lut, dtype=np.uint8)
+    rounds = _check(_load().oracle_thin_p_lut(s.ctypes.data_as(U8P), kp, p.ctypes.data_as(U32P),
+                                              s.shape[0], s.shape[1], l.ctypes.data_as(U8P)),
+                    "thin_lut")
+    return s, rounds
+
+
+def thicken_p(S, V, P, queue: bool = False):
+    s = np.ascontiguousarray(S, dtype=np.uint8).copy()
+    v, vp = _opt_u8(V)
+    p = np.ascontiguousarray(P, dtype=np.uint32)
+    fn = _load().oracle_thicken_queue_p if queue else _load().oracle_thicken_p
+    rounds = _check(fn(s.ctypes.data_as(U8P), vp, p.ctypes.data_as(U32P), s.shape[0], s.shape[1]),
+                    "thicken")
+    return s, rounds
+
+
+def homotopic_thin(X, K=None) -> np.ndarray:
+    x = np.ascontiguousarray(X, dtype=np.uint8).copy()
+    k, kp = _opt_u8(K)
+    _check(_load().oracle_homotopic_thin(x.ctypes.data_as(U8P), kp, x.shape[0], x.shape[1]),
+           "homotopic_thin")
+    return x
+
+
+def homotopic_thicken(Y, V) -> np.ndarray:
+    y = np.ascontiguousarray(Y, dtype=np.uint8).copy()
+    v, vp = _opt_u8(V)
+    _check(_load().oracle_homotopic_thicken(y.ctypes.data_as(U8P), vp, y.shape[0], y.shape[1]),
+           "homotopic_thicken")
+    return y
+
+
+def hc(X, C, i: int) -> np.ndarray:
+    x = np.ascontiguousarray(X, dtype=np.uint8).copy()
+    c, cp = _opt_u8(C)
+    _check(_load().oracle_hc(x.ctypes.data_as(U8P), cp, x.shape[0], x.shape[1], i), "hc")
+    return x
+
+
+def hf(X, i: int) -> np.ndarray:
+    x = np.ascontiguousarray(X, dtype=np.uint8).copy()
+    _check(_load().oracle_hf(x.ctypes.data_as(U8P), x.shape[0], x.shape[1], i), "hf")
+    return x
+
+
+def hasf(X, C, r: int, stages: bool = False, queue: bool = False):
+    """HASF of order r; with stages=True also returns an (r, 4, H, W) stage dump."""
+    x = np.ascontiguousarray(X, dtype=np.uint8).copy()
+    c, cp = _opt_u8(C)
+    H, W = x.shape
+    if queue:
+        _check(_load().oracle_hasf_queue(x.ctypes.data_as(U8P), cp, H, W, r), "hasf_queue")
+        return x
+    st = np.zeros((max(r, 1), 4, H, W), dtype=np.uint8) if stages else None
+    _check(_load().oracle_hasf(x.ctypes.data_as(U8P), cp, H, W, r,
+                               st.ctypes.data_as(U8P) if st is not None else None), "hasf")
+    return (x, st[:r]) if stages else x
