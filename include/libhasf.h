@@ -1,0 +1,158 @@
+/*
+ * libhasf -- homotopic alternating sequential filter (HASF) on 2D binary
+ * images, (8,4) connectivity, for AMD Instinct MI355X (gfx950).
+ *
+ * The method is the topology-preserving smoother of Mahmoudi & Akil,
+ * "Real Time Topological Image Smoothing On Shared Memory Parallel
+ * Machines" (arXiv:1603.09337), Sec. 2 and Sec. 4.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - An image is H x W bytes, row-major, row pitch `ld` bytes (ld >= W).
+ *    A nonzero byte is an object pixel; outputs are written as 0 or 1, and
+ *    only the first W bytes of each row are read or written.
+ *  - The plane outside the H x W window is background and never changes.
+ *  - Image pointers are DEVICE pointers (e.g. torch tensors' data_ptr()).
+ *    The caller owns them; the library never frees them.
+ *  - Every call that touches the device is enqueued on the context's stream
+ *    (hasf_set_stream) and is asynchronous to the host; hasf_sync() waits
+ *    and reports a device error. Arguments are validated on the host before
+ *    any device work; a rejected call enqueues nothing.
+ *  - Limits: 1 <= H, 1 <= W, H + W <= 65535; 0 <= r <= HASF_R_MAX.
+ *  - A context is used by one host thread at a time.
+ *  - No C++ exception crosses this interface; every call returns a status.
+ *
+ * Thinning and thickening follow one deterministic schedule (the order the
+ * paper leaves free is fixed so that results are reproducible bit for bit):
+ * distance levels in increasing order; inside a level, rounds of four passes
+ * over the 2x2 parity subfields (even,even), (even,odd), (odd,even),
+ * (odd,odd) of (row, column) relative to the image origin, each pass acting
+ * on the state left by the previous one, until a round changes nothing.
+ */
+#ifndef LIBHASF_H
+#define LIBHASF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HASF_OK = 0,
+    HASF_EINVAL = -1,     /* bad argument; nothing was enqueued */
+    HASF_ENOMEM = -2,     /* device or host allocation failed */
+    HASF_EDEVICE = -3,    /* a HIP call failed; see hasf_last_error */
+    HASF_EAGAIN = -4,     /* server queue full (non-blocking submit) */
+    HASF_ETIMEDOUT = -5,  /* wait timed out */
+    HASF_EINTERNAL = -6   /* internal invariant violated */
+} hasf_status;
+
+/* Largest radius accepted by hasf_filter / hasf_filter_batch. */
+#define HASF_R_MAX 15
+
+typedef struct hasf_ctx hasf_ctx;
+
+typedef struct {
+    int device;           /* HIP device ordinal */
+    size_t hbm_budget;    /* bytes the server may hold for frames; 0 = 1/4 of device memory */
+    unsigned flags;       /* reserved, must be 0 */
+} hasf_opts;
+
+/* Create a context on opts->device (opts may be NULL: device 0, defaults).
+ * The context owns its scratch memory and the default (null) stream. */
+hasf_status hasf_create(const hasf_opts* opts, hasf_ctx** out);
+void hasf_destroy(hasf_ctx* ctx);
+
+/* Use `hip_stream` (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream)
+ * for every later call on ctx. NULL selects the null stream. */
+hasf_status hasf_set_stream(hasf_ctx* ctx, void* hip_stream);
+
+/* Wait for ctx's stream; returns HASF_EDEVICE if queued device work failed. */
+hasf_status hasf_sync(hasf_ctx* ctx);
+
+const char* hasf_strerror(int status);
+/* Detail of the last failure on ctx (ctx may be NULL: last failure on this thread). */
+const char* hasf_last_error(const hasf_ctx* ctx);
+
+/*
+ * Simple-point table (Sec. 2, topological numbers T and T-bar; a point is
+ * simple iff T = 1 and T-bar = 1). Host-only, pure.
+ *   n = 8: object 8-adjacency, background 4-adjacency (the filter's pair);
+ *   n = 4: object 4-adjacency, background 8-adjacency.
+ * bits[m >> 5] bit (m & 31) is set iff neighbourhood code m is simple. Bit k
+ * of m is neighbour k in the order E, NE, N, NW, W, SW, S, SE
+ * (offsets (0,+1) (-1,+1) (-1,0) (-1,-1) (0,-1) (+1,-1) (+1,0) (+1,+1) in
+ * (row, column)). HASF_EINVAL for other n or bits == NULL.
+ */
+hasf_status hasf_simple_lut(int n, uint32_t bits[8]);
+
+/*
+ * Exact squared Euclidean distance transform (Sec. 4.1):
+ *   d2[i*ld_out + j] = min over feature pixels q of (i - qi)^2 + (j - qj)^2,
+ * where the features are the nonzero bytes of feat (pitch ld) and, when
+ * border_is_feature != 0, every pixel outside the window. With no feature at
+ * all the result is UINT32_MAX everywhere. d2 is a device array of H rows of
+ * ld_out >= W uint32 elements. feat and d2 must not overlap.
+ */
+hasf_status hasf_edt_sq(hasf_ctx* ctx, const uint8_t* feat, int H, int W, int64_t ld,
+                        int border_is_feature, uint32_t* d2, int64_t ld_out);
+
+/*
+ * Constrained homotopic thinning H(X, K) (Sec. 2): repeatedly deletes simple
+ * points of X that are not in K, in increasing order of their squared
+ * Euclidean distance to the background (outside of the window included),
+ * computed once before thinning; ends when no such point is simple (the
+ * constrained ultimate skeleton). X is updated in place. K may be NULL (empty)
+ * and shares X's pitch.
+ */
+hasf_status hasf_homotopic_thin(hasf_ctx* ctx, uint8_t* X, const uint8_t* K, int H, int W,
+                                int64_t ld);
+
+/*
+ * Constrained homotopic thickening *H(Y, V) (Sec. 2): repeatedly adds points
+ * of V (inside the window) that are simple for the complement of Y, in
+ * increasing order of their squared distance to Y, until stable. Y is updated
+ * in place; V shares Y's pitch and must not be NULL.
+ */
+hasf_status hasf_homotopic_thicken(hasf_ctx* ctx, uint8_t* Y, const uint8_t* V, int H, int W,
+                                   int64_t ld);
+
+/*
+ * HASF of order r with constraint set C (Sec. 2):
+ *   X <- HF_r o HC_r o ... o HF_1 o HC_1 (X), in place, where for radius i
+ *   HC_i(X) = *H(Y, V), Y = H(X, eps_i(X) u C), V = delta_i(Y) n X      (eq. i)
+ *   HF_i(X) = H(Z, W),  Z = *H(X, delta_i(X)), W = eps_i(Z) u X          (eq. ii)
+ * with Euclidean balls of radius i, thinning priority = squared distance to
+ * the background, thickening priority = squared distance to the set being
+ * thickened. C may be NULL (empty); C is intersected with X. r = 0 leaves X
+ * unchanged (apart from normalising it to 0/1). No background constraint set
+ * D is taken (D = empty).
+ */
+hasf_status hasf_filter(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, int H, int W, int64_t ld,
+                        int r);
+
+/* One image of a batch. */
+typedef struct {
+    uint8_t* X;        /* device, in/out */
+    const uint8_t* C;  /* device or NULL */
+    int H, W;
+    int64_t ld;
+    int r;
+} hasf_image;
+
+/*
+ * hasf_filter on n independent images of any sizes and radii, in one
+ * persistent launch: each workgroup claims images from a queue ordered by
+ * decreasing cost and filters them whole. The descriptor array is a host
+ * array; it is copied before the call returns. Images must not overlap.
+ * The result of each image equals hasf_filter on that image alone.
+ */
+hasf_status hasf_filter_batch(hasf_ctx* ctx, const hasf_image* imgs, int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBHASF_H */

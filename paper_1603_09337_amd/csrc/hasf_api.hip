@@ -1,0 +1,460 @@
+// C ABI of libhasf: context, errors, validation, scratch and launches.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "hasf_common.h"
+
+namespace hasf_detail {
+hipError_t launch_filter(const ImgDesc* d_desc, int n, int* d_next, int grid, size_t lds_bytes,
+                         hipStream_t stream);
+int filter_block();
+size_t edt_scratch_bytes(int H, int W);
+hipError_t launch_edt(const uint8_t* F, int H, int W, long long ld, int frame, int invert, uint32_t* d2,
+                      long long ldo, void* scratch, size_t lds_max, hipStream_t stream);
+hipError_t launch_topo(const TopoArgs& a, size_t lds_bytes, hipStream_t stream);
+int filter_occupancy(size_t lds_bytes);
+}  // namespace hasf_detail
+
+using namespace hasf_detail;
+
+namespace {
+
+thread_local char t_err[512] = "";
+
+void set_err(hasf_ctx* ctx, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    std::strncpy(t_err, buf, sizeof t_err - 1);
+    if (ctx)
+        std::strncpy(ctx->err, buf, sizeof ctx->err - 1);
+}
+
+hasf_status dev_fail(hasf_ctx* ctx, hipError_t e, const char* what)
+{
+    set_err(ctx, "%s: %s", what, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? HASF_ENOMEM : HASF_EDEVICE;
+}
+
+hasf_status check_image(hasf_ctx* ctx, const void* X, int H, int W, int64_t ld, const char* what)
+{
+    if (!ctx) {
+        set_err(nullptr, "%s: ctx is NULL", what);
+        return HASF_EINVAL;
+    }
+    if (!X) {
+        set_err(ctx, "%s: image pointer is NULL", what);
+        return HASF_EINVAL;
+    }
+    if (H < 1 || W < 1 || (int64_t)H + W > 65535) {
+        set_err(ctx, "%s: need 1 <= H, 1 <= W, H + W <= 65535 (got H=%d W=%d)", what, H, W);
+        return HASF_EINVAL;
+    }
+    if (ld < W) {
+        set_err(ctx, "%s: ld (%lld) < W (%d)", what, (long long)ld, W);
+        return HASF_EINVAL;
+    }
+    return HASF_OK;
+}
+
+// grow-only device scratch; waits for queued work before replacing it
+hasf_status ensure_scratch(hasf_ctx* ctx, size_t bytes)
+{
+    if (bytes <= ctx->scratch_bytes)
+        return HASF_OK;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "hipStreamSynchronize");
+    if (ctx->scratch)
+        hipFree(ctx->scratch);
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+    size_t want = std::max(bytes, (size_t)64 << 20);
+    e = hipMalloc(&ctx->scratch, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return dev_fail(ctx, e, "hipMalloc(scratch)");
+    }
+    ctx->scratch_bytes = want;
+    return HASF_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+int levels_host(int r)
+{
+    int c = 0;
+    for (int v = 1; v <= r * r; ++v)
+        if (is_sum_two_squares(v))
+            ++c;
+    return c;
+}
+
+struct Layout {
+    size_t bytes;
+    std::vector<size_t> off;  // per image: gplanes, ent_idx, ent_msk offsets (3 each)
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* hasf_strerror(int s)
+{
+    switch (s) {
+    case HASF_OK: return "ok";
+    case HASF_EINVAL: return "invalid argument";
+    case HASF_ENOMEM: return "out of memory";
+    case HASF_EDEVICE: return "device error";
+    case HASF_EAGAIN: return "try again";
+    case HASF_ETIMEDOUT: return "timed out";
+    case HASF_EINTERNAL: return "internal error";
+    default: return "unknown status";
+    }
+}
+
+const char* hasf_last_error(const hasf_ctx* ctx)
+{
+    return ctx ? ctx->err : t_err;
+}
+
+hasf_status hasf_simple_lut(int n, uint32_t bits[8])
+{
+    if (!bits || (n != 8 && n != 4)) {
+        set_err(nullptr, "hasf_simple_lut: need n in {4, 8} and bits != NULL");
+        return HASF_EINVAL;
+    }
+    for (int k = 0; k < 8; ++k)
+        bits[k] = 0;
+    for (unsigned m = 0; m < 256; ++m) {
+        // (4,8)-simple for code m  <=>  (8,4)-simple for the complementary code
+        const unsigned c = n == 8 ? m : (~m & 0xFFu);
+        unsigned x[8];
+        for (int k = 0; k < 8; ++k)
+            x[k] = (c >> k) & 1u;
+        const unsigned s = simple_bits<unsigned>(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7]) & 1u;
+        bits[m >> 5] |= s << (m & 31);
+    }
+    return HASF_OK;
+}
+
+hasf_status hasf_create(const hasf_opts* opts, hasf_ctx** out)
+{
+    if (!out) {
+        set_err(nullptr, "hasf_create: out is NULL");
+        return HASF_EINVAL;
+    }
+    *out = nullptr;
+    hasf_opts o{};
+    if (opts)
+        o = *opts;
+    if (o.flags != 0) {
+        set_err(nullptr, "hasf_create: flags must be 0");
+        return HASF_EINVAL;
+    }
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0) {
+        set_err(nullptr, "hasf_create: no HIP device (%s)", hipGetErrorString(e));
+        return HASF_EDEVICE;
+    }
+    if (o.device < 0 || o.device >= ndev) {
+        set_err(nullptr, "hasf_create: device %d out of range [0, %d)", o.device, ndev);
+        return HASF_EINVAL;
+    }
+    e = hipSetDevice(o.device);
+    if (e != hipSuccess)
+        return dev_fail(nullptr, e, "hipSetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, o.device);
+    if (e != hipSuccess)
+        return dev_fail(nullptr, e, "hipGetDeviceProperties");
+    hasf_ctx* c = new (std::nothrow) hasf_ctx();
+    if (!c) {
+        set_err(nullptr, "hasf_create: out of host memory");
+        return HASF_ENOMEM;
+    }
+    c->device = o.device;
+    c->stream = nullptr;
+    c->num_cu = prop.multiProcessorCount;
+    c->lds_per_block = prop.sharedMemPerBlock;
+    c->hbm_budget = o.hbm_budget ? o.hbm_budget : prop.totalGlobalMem / 4;
+    c->err[0] = 0;
+    c->scratch = nullptr;
+    c->scratch_bytes = 0;
+    c->d_desc = nullptr;
+    c->desc_cap = 0;
+    c->d_counter = nullptr;
+    *out = c;
+    return HASF_OK;
+}
+
+void hasf_destroy(hasf_ctx* ctx)
+{
+    if (!ctx)
+        return;
+    hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    if (ctx->scratch)
+        hipFree(ctx->scratch);
+    if (ctx->d_desc)
+        hipFree(ctx->d_desc);
+    delete ctx;
+}
+
+hasf_status hasf_set_stream(hasf_ctx* ctx, void* hip_stream)
+{
+    if (!ctx) {
+        set_err(nullptr, "hasf_set_stream: ctx is NULL");
+        return HASF_EINVAL;
+    }
+    ctx->stream = (hipStream_t)hip_stream;
+    return HASF_OK;
+}
+
+hasf_status hasf_sync(hasf_ctx* ctx)
+{
+    if (!ctx) {
+        set_err(nullptr, "hasf_sync: ctx is NULL");
+        return HASF_EINVAL;
+    }
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "hipStreamSynchronize");
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "device");
+    return HASF_OK;
+}
+
+hasf_status hasf_edt_sq(hasf_ctx* ctx, const uint8_t* feat, int H, int W, int64_t ld, int border_is_feature,
+                        uint32_t* d2, int64_t ld_out)
+{
+    hasf_status s = check_image(ctx, feat, H, W, ld, "hasf_edt_sq");
+    if (s)
+        return s;
+    if (!d2 || ld_out < W) {
+        set_err(ctx, "hasf_edt_sq: need d2 != NULL and ld_out >= W");
+        return HASF_EINVAL;
+    }
+    hipSetDevice(ctx->device);
+    if ((s = ensure_scratch(ctx, edt_scratch_bytes(H, W))))
+        return s;
+    const size_t lds_max = std::min(ctx->lds_per_block, (size_t)160 * 1024);
+    hipError_t e = launch_edt(feat, H, W, ld, border_is_feature ? 1 : 0, 0, d2, ld_out, ctx->scratch, lds_max,
+                              ctx->stream);
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "hasf_edt_sq launch");
+    return HASF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// filter and batch
+// ---------------------------------------------------------------------------
+namespace {
+
+hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char* what)
+{
+    if (!ctx) {
+        set_err(nullptr, "%s: ctx is NULL", what);
+        return HASF_EINVAL;
+    }
+    if (n < 0 || (n > 0 && !imgs)) {
+        set_err(ctx, "%s: bad image array", what);
+        return HASF_EINVAL;
+    }
+    for (int k = 0; k < n; ++k) {
+        hasf_status s = check_image(ctx, imgs[k].X, imgs[k].H, imgs[k].W, imgs[k].ld, what);
+        if (s)
+            return s;
+        if (imgs[k].r < 0 || imgs[k].r > HASF_R_MAX) {
+            set_err(ctx, "%s: image %d: r = %d outside [0, %d]", what, k, imgs[k].r, HASF_R_MAX);
+            return HASF_EINVAL;
+        }
+    }
+    if (n == 0)
+        return HASF_OK;
+    hipSetDevice(ctx->device);
+
+    // queue order: decreasing cost (pixels x levels of the whole radius loop)
+    std::vector<int> order(n);
+    std::vector<double> cost(n);
+    for (int k = 0; k < n; ++k) {
+        order[k] = k;
+        double lv = 0;
+        for (int i = 1; i <= imgs[k].r; ++i)
+            lv += levels_host(i) + 1;
+        cost[k] = (double)imgs[k].H * imgs[k].W * (lv + 1);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+
+    const size_t lds_cap = std::min(ctx->lds_per_block, (size_t)160 * 1024) - 2048;
+    std::vector<ImgDesc> desc(n);
+    size_t bytes = 0, lds_need = 0;
+    for (int q = 0; q < n; ++q) {
+        const hasf_image& im = imgs[order[q]];
+        const size_t WW = (size_t)(im.W + 63) / 64;
+        const size_t NWD = (size_t)im.H * WW;
+        const bool lds = 2 * NWD * 8 <= lds_cap;
+        const size_t nlev = (size_t)std::max(1, levels_host(im.r));
+        ImgDesc& d = desc[q];
+        d.X = im.X;
+        d.C = im.C;
+        d.ld = im.ld;
+        d.H = im.H;
+        d.W = im.W;
+        d.r = im.r;
+        d.lds = lds ? 1 : 0;
+        if (lds)
+            lds_need = std::max(lds_need, 2 * NWD * 8);
+        // offsets for now; rebased after allocation
+        d.gplanes = (uint64_t*)bytes;
+        bytes += align256((lds ? 2 : 4) * NWD * 8);
+        d.ent_idx = (uint32_t*)bytes;
+        bytes += align256(nlev * NWD * 4);
+        d.ent_msk = (uint64_t*)bytes;
+        bytes += align256(nlev * NWD * 8);
+    }
+    const size_t desc_bytes = align256(256 + sizeof(ImgDesc) * (size_t)n);
+    hasf_status s = ensure_scratch(ctx, bytes + desc_bytes);
+    if (s)
+        return s;
+    char* base = (char*)ctx->scratch;
+    for (auto& d : desc) {
+        d.gplanes = (uint64_t*)(base + desc_bytes + (size_t)d.gplanes);
+        d.ent_idx = (uint32_t*)(base + desc_bytes + (size_t)d.ent_idx);
+        d.ent_msk = (uint64_t*)(base + desc_bytes + (size_t)d.ent_msk);
+    }
+    // [counter | descriptors] in one copy: the counter starts at 0
+    std::vector<char> host(desc_bytes, 0);
+    std::memcpy(host.data() + 256, desc.data(), sizeof(ImgDesc) * (size_t)n);
+    hipError_t e = hipMemcpyAsync(base, host.data(), 256 + sizeof(ImgDesc) * (size_t)n, hipMemcpyHostToDevice,
+                                  ctx->stream);
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "hipMemcpyAsync(descriptors)");
+    // the pageable source must stay alive until the copy has consumed it
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "hipStreamSynchronize(descriptors)");
+    const int occ = std::max(1, filter_occupancy(lds_need));
+    const int grid = std::min(n, ctx->num_cu * occ);
+    e = launch_filter((const ImgDesc*)(base + 256), n, (int*)base, grid, lds_need, ctx->stream);
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "hasf_filter launch");
+    return HASF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hasf_status hasf_filter(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, int H, int W, int64_t ld, int r)
+{
+    hasf_image im;
+    im.X = X;
+    im.C = C;
+    im.H = H;
+    im.W = W;
+    im.ld = ld;
+    im.r = r;
+    return run_images(ctx, &im, 1, "hasf_filter");
+}
+
+hasf_status hasf_filter_batch(hasf_ctx* ctx, const hasf_image* imgs, int n)
+{
+    return run_images(ctx, imgs, n, "hasf_filter_batch");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// standalone thinning / thickening
+// ---------------------------------------------------------------------------
+namespace {
+
+hasf_status run_topo(hasf_ctx* ctx, uint8_t* X, const uint8_t* B, int H, int W, int64_t ld, bool thin,
+                     const char* what)
+{
+    hasf_status s = check_image(ctx, X, H, W, ld, what);
+    if (s)
+        return s;
+    if (!thin && !B) {
+        set_err(ctx, "%s: V must not be NULL", what);
+        return HASF_EINVAL;
+    }
+    hipSetDevice(ctx->device);
+    const size_t N = (size_t)H * W;
+    const size_t WW = (size_t)(W + 63) / 64, NWD = (size_t)H * WW;
+    // largest priority value: distance to the outside (thin) or anywhere in the window
+    unsigned long long vmax;
+    if (thin) {
+        const unsigned long long m = (unsigned long long)std::min((H + 1) / 2, (W + 1) / 2);
+        vmax = m * m;
+    } else {
+        vmax = (unsigned long long)(H - 1) * (H - 1) + (unsigned long long)(W - 1) * (W - 1);
+    }
+    const unsigned long long nbw = vmax / 64 + 1;
+    const size_t lds_cap = std::min(ctx->lds_per_block, (size_t)160 * 1024) - 4096;
+    const bool lds = 2 * NWD * 8 <= lds_cap;
+    size_t off = 0;
+    const size_t oP = off; off += align256(N * 4);
+    const size_t oE = off; off += align256(edt_scratch_bytes(H, W));
+    const size_t oPl = off; off += align256(3 * NWD * 8);
+    const size_t oBm = off; off += align256(nbw * 8);
+    const size_t oRb = off; off += align256(nbw * 4);
+    const size_t oH = off; off += align256((N + 1) * 4);
+    const size_t oEn = off; off += align256(N * 4);
+    if ((s = ensure_scratch(ctx, off)))
+        return s;
+    char* base = (char*)ctx->scratch;
+    const size_t lds_max = std::min(ctx->lds_per_block, (size_t)160 * 1024);
+    // thinning: distance to the background (zero bytes of X) and the outside
+    hipError_t e = launch_edt(X, H, W, ld, thin ? 1 : 0, thin ? 1 : 0, (uint32_t*)(base + oP), W, base + oE,
+                              lds_max, ctx->stream);
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "edt launch");
+    TopoArgs a;
+    a.X = X;
+    a.B = B;
+    a.ld = ld;
+    a.H = H;
+    a.W = W;
+    a.thin = thin ? 1 : 0;
+    a.lds = lds ? 1 : 0;
+    a.P = (const uint32_t*)(base + oP);
+    a.planes = (uint64_t*)(base + oPl);
+    a.bitmap = (uint64_t*)(base + oBm);
+    a.rank_base = (uint32_t*)(base + oRb);
+    a.hist = (uint32_t*)(base + oH);
+    a.ent = (uint32_t*)(base + oEn);
+    a.nbw = nbw;
+    e = launch_topo(a, lds ? 2 * NWD * 8 : 0, ctx->stream);
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "topo launch");
+    return HASF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hasf_status hasf_homotopic_thin(hasf_ctx* ctx, uint8_t* X, const uint8_t* K, int H, int W, int64_t ld)
+{
+    return run_topo(ctx, X, K, H, W, ld, true, "hasf_homotopic_thin");
+}
+
+hasf_status hasf_homotopic_thicken(hasf_ctx* ctx, uint8_t* Y, const uint8_t* V, int H, int W, int64_t ld)
+{
+    return run_topo(ctx, Y, V, H, W, ld, false, "hasf_homotopic_thicken");
+}
+
+}  // extern "C"

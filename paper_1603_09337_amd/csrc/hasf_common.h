@@ -1,0 +1,152 @@
+// Shared host/device definitions of libhasf: the bit-sliced simple-point
+// test, level tables for Euclidean balls, and the context structure.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "libhasf.h"
+
+#define HASF_HD __host__ __device__ __forceinline__
+
+// ---------------------------------------------------------------------------
+// Simple-point test (Sec. 2). For (8,4), a point with neighbours x0..x7
+// (E NE N NW W SW S SE) is simple iff T = T-bar = 1. Counting, around the
+// ring, the background 4-neighbours x_2k whose counter-clockwise successor
+// path x_2k+1, x_2k+2 is not all background gives the number of background
+// 4-components touching the centre (Yokoi's 8-connectivity number); the
+// point is simple exactly when that count is 1 (an isolated point and an
+// interior point both give 0). The test is written on words so that it
+// evaluates 64 pixels (one per bit) at once; hasf_simple_lut evaluates the
+// same function on single bits, and the tests compare that table with an
+// independent component-counting table on all 256 codes.
+// ---------------------------------------------------------------------------
+template <typename T>
+HASF_HD T simple_bits(T x0, T x1, T x2, T x3, T x4, T x5, T x6, T x7)
+{
+    const T t0 = ~x0 & (x1 | x2);
+    const T t1 = ~x2 & (x3 | x4);
+    const T t2 = ~x4 & (x5 | x6);
+    const T t3 = ~x6 & (x7 | x0);
+    // exactly one of t0..t3
+    return (t0 ^ t1 ^ t2 ^ t3) & ~((t0 & t1) | (t2 & t3));
+}
+
+// ---------------------------------------------------------------------------
+// Euclidean balls. Offsets (a, b), a, b >= 0, with a^2 + b^2 <= R^2, sorted by
+// v = a^2 + b^2: a pixel whose nearest feature lies at row offset +-a and
+// column offset +-b has squared distance v. rank(v) = number of sums of two
+// squares in [1, v): consecutive distinct values of v are consecutive levels.
+// ---------------------------------------------------------------------------
+constexpr int HASF_V_MAX = HASF_R_MAX * HASF_R_MAX;
+
+struct BallPairs {
+    int n;
+    unsigned char a[256];
+    unsigned char b[256];
+    unsigned short v[256];
+    unsigned char rank[256];
+};
+
+constexpr bool is_sum_two_squares(int v)
+{
+    for (int a = 0; a * a <= v; ++a)
+        for (int b = 0; a * a + b * b <= v; ++b)
+            if (a * a + b * b == v)
+                return true;
+    return false;
+}
+
+constexpr int level_count(int R)  // distinct nonzero squared distances <= R^2
+{
+    bool hit[HASF_V_MAX + 1] = {};
+    for (int a = 0; a <= R; ++a)
+        for (int b = 0; a * a + b * b <= R * R; ++b)
+            hit[a * a + b * b] = true;
+    int c = 0;
+    for (int v = 1; v <= R * R; ++v)
+        c += hit[v] ? 1 : 0;
+    return c;
+}
+
+constexpr BallPairs make_ball_pairs(int R)
+{
+    BallPairs p{};
+    bool hit[HASF_V_MAX + 1] = {};
+    for (int a = 0; a <= R; ++a)
+        for (int b = 0; a * a + b * b <= R * R; ++b)
+            hit[a * a + b * b] = true;
+    p.n = 0;
+    int rk = 0;
+    for (int v = 1; v <= R * R; ++v) {
+        if (!hit[v])
+            continue;
+        for (int a = 0; a <= R; ++a)
+            for (int b = 0; b <= R; ++b)
+                if (a * a + b * b == v) {
+                    p.a[p.n] = (unsigned char)a;
+                    p.b[p.n] = (unsigned char)b;
+                    p.v[p.n] = (unsigned short)v;
+                    p.rank[p.n] = (unsigned char)rk;
+                    ++p.n;
+                }
+        ++rk;
+    }
+    return p;
+}
+
+static_assert(level_count(10) == 43, "levels at radius 10");
+static_assert(make_ball_pairs(HASF_R_MAX).n <= 256, "ball offsets");
+static_assert(level_count(HASF_R_MAX) <= 128, "level counters");
+constexpr int HASF_LEVELS_MAX = level_count(HASF_R_MAX);
+
+// ---------------------------------------------------------------------------
+// Per-image descriptor used by the persistent filter kernel.
+// ---------------------------------------------------------------------------
+struct ImgDesc {
+    uint8_t* X;
+    const uint8_t* C;
+    long long ld;
+    int H, W, r;
+    int lds;            // 1: S and M planes in LDS; 0: in gplanes
+    uint64_t* gplanes;  // S, M (when lds == 0), A (saved set), K (constraint)
+    uint32_t* ent_idx;  // level entries: word index, levels(r) x words
+    uint64_t* ent_msk;  // level entries: candidate bits
+};
+
+// Arguments of the standalone thinning / thickening kernel.
+namespace hasf_detail {
+
+struct TopoArgs {
+    uint8_t* X;
+    const uint8_t* B;  // K (thin) or V (thicken); may be NULL for thin
+    long long ld;
+    int H, W;
+    int thin;
+    int lds;                // S and M planes in LDS
+    const uint32_t* P;      // priorities, pitch W
+    uint64_t* planes;       // S, M (when lds == 0), Bp
+    uint64_t* bitmap;       // one bit per priority value
+    uint32_t* rank_base;    // per bitmap word: number of set bits before it
+    uint32_t* hist;         // per level: end offset after the scatter
+    uint32_t* ent;          // candidate pixels grouped by level
+    unsigned long long nbw; // bitmap words
+};
+
+}  // namespace hasf_detail
+
+// host-side context
+struct hasf_ctx {
+    int device;
+    hipStream_t stream;
+    size_t hbm_budget;
+    int num_cu;
+    size_t lds_per_block;
+    char err[512];
+    // growable device scratch
+    void* scratch;
+    size_t scratch_bytes;
+    ImgDesc* d_desc;
+    int desc_cap;
+    int* d_counter;
+};

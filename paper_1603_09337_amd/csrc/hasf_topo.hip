@@ -1,0 +1,228 @@
+// Standalone constrained thinning H(X, K) and thickening *H(Y, V) (Sec. 2)
+// with exact priorities: the squared Euclidean distance to the background
+// (thinning, outside of the window included) or to Y (thickening), computed
+// once by the exact transform before the first level.
+//
+// One workgroup runs the whole schedule. The distinct priority values of the
+// candidates are the levels: they are ranked with a bitmap over the value
+// range and a prefix popcount, the candidates are bucketed by rank (counting
+// sort), and the levels are then processed in increasing order with the same
+// subfield rounds as the filter.
+#include "hasf_device.h"
+
+using namespace hasf_dev;
+
+
+using hasf_detail::TopoArgs;
+
+namespace {
+
+typedef __attribute__((address_space(1))) uint32_t g32;
+
+// exclusive scan of per-thread values over the block; returns the total
+__device__ unsigned block_exclusive_scan(unsigned v, unsigned* out_prefix, unsigned* lds_tmp)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned y = __shfl_up(x, o);
+        if (lane >= o)
+            x += y;
+    }
+    if (lane == 63)
+        lds_tmp[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned acc = 0;
+        for (int w = 0; w < BLOCK / 64; ++w) {
+            const unsigned t = lds_tmp[w];
+            lds_tmp[w] = acc;
+            acc += t;
+        }
+        lds_tmp[BLOCK / 64] = acc;
+    }
+    __syncthreads();
+    *out_prefix = lds_tmp[wave] + x - v;
+    const unsigned total = lds_tmp[BLOCK / 64];
+    __syncthreads();
+    return total;
+}
+
+template <typename PP>
+__device__ __forceinline__ bool bit_at(PP plane, int WW, int i, int j)
+{
+    return (plane[i * WW + (j >> 6)] >> (j & 63)) & 1ull;
+}
+
+template <bool LDS>
+__device__ void topo_run(const TopoArgs& a, uint64_t* smem)
+{
+    __shared__ unsigned tmp[BLOCK / 64 + 1];
+    Img<LDS> g;
+    g.H = a.H;
+    g.W = a.W;
+    g.WW = (a.W + 63) >> 6;
+    g.NWD = g.H * g.WW;
+    g.lastmask = (a.W & 63) ? ((1ull << (a.W & 63)) - 1ull) : ~0ull;
+    glb_u64* gp = (glb_u64*)a.planes;
+    if constexpr (LDS) {
+        g.S = (lds_u64*)smem;
+        g.M = (lds_u64*)smem + g.NWD;
+    } else {
+        g.S = gp;
+        g.M = gp + g.NWD;
+    }
+    glb_u64* Bp = gp + 2 * (size_t)g.NWD;
+    g.A = Bp;
+    g.K = Bp;
+    g.hasK = false;
+    g.eidx = nullptr;
+    g.emsk = nullptr;
+    const int N = a.H * a.W;
+
+    // X -> S; B -> Bp (pack_image writes X's bits; B is packed on its own)
+    pack_image(a.X, (const uint8_t*)nullptr, a.ld, g);
+    {
+        Img<false> gb;
+        gb.H = g.H;
+        gb.W = g.W;
+        gb.WW = g.WW;
+        gb.NWD = g.NWD;
+        gb.S = Bp;
+        gb.hasK = false;
+        if (a.B)
+            pack_image(a.B, (const uint8_t*)nullptr, a.ld, gb);
+        else
+            for (int q = threadIdx.x; q < g.NWD; q += BLOCK)
+                Bp[q] = 0;
+    }
+    for (int q = threadIdx.x; q < g.NWD; q += BLOCK)
+        g.M[q] = 0;
+    glb_u64* bm = (glb_u64*)a.bitmap;
+    for (unsigned long long q = threadIdx.x; q < a.nbw; q += BLOCK)
+        bm[q] = 0;
+    __syncthreads();
+
+    // mark the priority values of the candidates
+    for (int p = threadIdx.x; p < N; p += BLOCK) {
+        const int i = p / a.W, j = p - i * a.W;
+        const bool s = bit_at(g.S, g.WW, i, j), b = bit_at(Bp, g.WW, i, j);
+        if (a.thin ? (s && !b) : (!s && b)) {
+            const uint32_t v = a.P[(size_t)i * a.W + j];
+            if (v != 0xFFFFFFFFu)
+                __hip_atomic_fetch_or(bm + (v >> 6), 1ull << (v & 63), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    __syncthreads();
+
+    // rank base of every bitmap word (prefix popcount, chunked per thread)
+    const unsigned long long chunk = (a.nbw + BLOCK - 1) / BLOCK;
+    const unsigned long long c0 = threadIdx.x * chunk, c1 = min(a.nbw, c0 + chunk);
+    unsigned local = 0;
+    for (unsigned long long q = c0; q < c1; ++q)
+        local += __popcll(bm[q]);
+    unsigned pre;
+    const unsigned nlev = block_exclusive_scan(local, &pre, tmp);
+    g32* rb = (g32*)a.rank_base;
+    for (unsigned long long q = c0; q < c1; ++q) {
+        rb[q] = pre;
+        pre += __popcll(bm[q]);
+    }
+    g32* hist = (g32*)a.hist;
+    for (unsigned k = threadIdx.x; k < nlev; k += BLOCK)
+        hist[k] = 0;
+    __syncthreads();
+
+    // count candidates per level
+    for (int p = threadIdx.x; p < N; p += BLOCK) {
+        const int i = p / a.W, j = p - i * a.W;
+        const bool s = bit_at(g.S, g.WW, i, j), b = bit_at(Bp, g.WW, i, j);
+        if (a.thin ? (s && !b) : (!s && b)) {
+            const uint32_t v = a.P[(size_t)i * a.W + j];
+            if (v != 0xFFFFFFFFu) {
+                const uint64_t w = bm[v >> 6];
+                const unsigned rk = rb[v >> 6] + __popcll(w & ((1ull << (v & 63)) - 1ull));
+                __hip_atomic_fetch_add(hist + rk, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+    }
+    __syncthreads();
+    // exclusive offsets per level
+    {
+        const unsigned long long hc = (nlev + BLOCK - 1) / BLOCK;
+        const unsigned long long h0 = threadIdx.x * hc, h1 = min((unsigned long long)nlev, h0 + hc);
+        unsigned loc = 0;
+        for (unsigned long long k = h0; k < h1; ++k)
+            loc += hist[k];
+        unsigned hp;
+        block_exclusive_scan(loc, &hp, tmp);
+        for (unsigned long long k = h0; k < h1; ++k) {
+            const unsigned c = hist[k];
+            hist[k] = hp;
+            hp += c;
+        }
+    }
+    __syncthreads();
+    // scatter: afterwards hist[k] is the end of level k
+    g32* ent = (g32*)a.ent;
+    for (int p = threadIdx.x; p < N; p += BLOCK) {
+        const int i = p / a.W, j = p - i * a.W;
+        const bool s = bit_at(g.S, g.WW, i, j), b = bit_at(Bp, g.WW, i, j);
+        if (a.thin ? (s && !b) : (!s && b)) {
+            const uint32_t v = a.P[(size_t)i * a.W + j];
+            if (v != 0xFFFFFFFFu) {
+                const uint64_t w = bm[v >> 6];
+                const unsigned rk = rb[v >> 6] + __popcll(w & ((1ull << (v & 63)) - 1ull));
+                const unsigned pos = __hip_atomic_fetch_add(hist + rk, 1u, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+                ent[pos] = (uint32_t)p;
+            }
+        }
+    }
+    __syncthreads();
+
+    // levels in increasing order
+    for (unsigned k = 0; k < nlev; ++k) {
+        const unsigned e0 = k ? hist[k - 1] : 0u, e1 = hist[k];
+        for (unsigned t = e0 + threadIdx.x; t < e1; t += BLOCK) {
+            const unsigned p = ent[t];
+            const int i = (int)(p / (unsigned)a.W), j = (int)(p - (unsigned)i * (unsigned)a.W);
+            __hip_atomic_fetch_or(g.M + (i * g.WW + (j >> 6)), 1ull << (j & 63), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __syncthreads();
+        run_rounds(g, a.thin != 0);
+    }
+    unpack_image(a.X, a.ld, g);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(BLOCK) void hasf_topo_kernel(TopoArgs a)
+{
+    extern __shared__ uint64_t smem[];
+    if (a.lds)
+        topo_run<true>(a, smem);
+    else
+        topo_run<false>(a, smem);
+}
+
+namespace hasf_detail {
+
+hipError_t launch_topo(const TopoArgs& a, size_t lds_bytes, hipStream_t stream)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)hasf_topo_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
+        if (e != hipSuccess)
+            return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(hasf_topo_kernel, dim3(1), dim3(BLOCK), lds_bytes, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace hasf_detail

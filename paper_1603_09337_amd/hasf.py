@@ -1,0 +1,174 @@
+"""ctypes binding of libhasf (argument marshalling only).
+
+Images are torch uint8 CUDA tensors of shape (H, W) with unit column stride;
+the row pitch is taken from ``stride(0)``. Every call is enqueued on the
+current torch stream of the context's device. No computation happens here:
+each function forwards to the C entry point of the same name.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libhasf.so")
+
+HASF_OK = 0
+HASF_EINVAL = -1
+HASF_ENOMEM = -2
+HASF_EDEVICE = -3
+HASF_EAGAIN = -4
+HASF_ETIMEDOUT = -5
+HASF_EINTERNAL = -6
+HASF_R_MAX = 15
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libhasf.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("hbm_budget", ctypes.c_size_t), ("flags", ctypes.c_uint)]
+
+
+class _Image(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("C", ctypes.c_void_p), ("H", ctypes.c_int), ("W", ctypes.c_int),
+                ("ld", ctypes.c_int64), ("r", ctypes.c_int)]
+
+
+_vp = ctypes.c_void_p
+_lib.hasf_create.argtypes = [ctypes.POINTER(_Opts), ctypes.POINTER(_vp)]
+_lib.hasf_destroy.argtypes = [_vp]
+_lib.hasf_destroy.restype = None
+_lib.hasf_set_stream.argtypes = [_vp, _vp]
+_lib.hasf_sync.argtypes = [_vp]
+_lib.hasf_strerror.argtypes = [ctypes.c_int]
+_lib.hasf_strerror.restype = ctypes.c_char_p
+_lib.hasf_last_error.argtypes = [_vp]
+_lib.hasf_last_error.restype = ctypes.c_char_p
+_lib.hasf_simple_lut.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_uint32)]
+_lib.hasf_edt_sq.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int, _vp,
+                             ctypes.c_int64]
+_lib.hasf_homotopic_thin.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64]
+_lib.hasf_homotopic_thicken.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64]
+_lib.hasf_filter.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int]
+_lib.hasf_filter_batch.argtypes = [_vp, ctypes.POINTER(_Image), ctypes.c_int]
+for _f in ("hasf_create", "hasf_set_stream", "hasf_sync", "hasf_simple_lut", "hasf_edt_sq",
+           "hasf_homotopic_thin", "hasf_homotopic_thicken", "hasf_filter", "hasf_filter_batch"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+class HasfError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__("%s (%d): %s" % (_lib.hasf_strerror(status).decode(), status, detail))
+        self.status = status
+
+
+def lib():
+    return _lib
+
+
+def exported_symbols():
+    return [n for n in ("hasf_create", "hasf_destroy", "hasf_set_stream", "hasf_sync", "hasf_strerror",
+                        "hasf_last_error", "hasf_simple_lut", "hasf_edt_sq", "hasf_homotopic_thin",
+                        "hasf_homotopic_thicken", "hasf_filter", "hasf_filter_batch")]
+
+
+def simple_lut(n: int = 8):
+    """256-entry simple-point table as a list of 0/1 (host-only)."""
+    bits = (ctypes.c_uint32 * 8)()
+    st = _lib.hasf_simple_lut(n, bits)
+    if st != HASF_OK:
+        raise HasfError(st, _lib.hasf_last_error(None).decode())
+    return [(bits[m >> 5] >> (m & 31)) & 1 for m in range(256)]
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _img(t, name):
+    if t.dtype.__repr__() != "torch.uint8" or t.dim() != 2 or t.stride(1) != 1 or not t.is_cuda:
+        raise ValueError("%s must be a 2D uint8 CUDA tensor with unit column stride" % name)
+    return t.shape[0], t.shape[1], t.stride(0)
+
+
+class Context:
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        import torch
+        self._torch = torch
+        self.device = device
+        h = _vp()
+        opts = _Opts(device, hbm_budget, 0)
+        st = _lib.hasf_create(ctypes.byref(opts), ctypes.byref(h))
+        if st != HASF_OK:
+            raise HasfError(st, _lib.hasf_last_error(None).decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hasf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != HASF_OK:
+            raise HasfError(st, _lib.hasf_last_error(self._h).decode())
+
+    def _stream(self):
+        s = self._torch.cuda.current_stream(self.device).cuda_stream
+        self._check(_lib.hasf_set_stream(self._h, _vp(s)))
+
+    def sync(self):
+        self._check(_lib.hasf_sync(self._h))
+
+    def edt_sq(self, feat, border_is_feature: bool = False, out=None):
+        H, W, ld = _img(feat, "feat")
+        if out is None:
+            out = self._torch.empty((H, W), dtype=self._torch.int32, device=feat.device)
+        self._stream()
+        self._check(_lib.hasf_edt_sq(self._h, _ptr(feat), H, W, ld, int(bool(border_is_feature)), _ptr(out),
+                                     out.stride(0)))
+        return out
+
+    def homotopic_thin(self, X, K=None):
+        H, W, ld = _img(X, "X")
+        if K is not None and (K.shape != X.shape or K.stride(0) != ld):
+            raise ValueError("K must match X's shape and pitch")
+        self._stream()
+        self._check(_lib.hasf_homotopic_thin(self._h, _ptr(X), _ptr(K), H, W, ld))
+        return X
+
+    def homotopic_thicken(self, Y, V):
+        H, W, ld = _img(Y, "Y")
+        if V is None or V.shape != Y.shape or V.stride(0) != ld:
+            raise ValueError("V must match Y's shape and pitch")
+        self._stream()
+        self._check(_lib.hasf_homotopic_thicken(self._h, _ptr(Y), _ptr(V), H, W, ld))
+        return Y
+
+    def filter(self, X, C=None, r: int = 1):
+        H, W, ld = _img(X, "X")
+        if C is not None and (C.shape != X.shape or C.stride(0) != ld):
+            raise ValueError("C must match X's shape and pitch")
+        self._stream()
+        self._check(_lib.hasf_filter(self._h, _ptr(X), _ptr(C), H, W, ld, r))
+        return X
+
+    def filter_batch(self, items):
+        """items: sequence of (X, C or None, r)."""
+        arr = (_Image * max(1, len(items)))()
+        for k, (X, C, r) in enumerate(items):
+            H, W, ld = _img(X, "X[%d]" % k)
+            if C is not None and (C.shape != X.shape or C.stride(0) != ld):
+                raise ValueError("C[%d] must match X's shape and pitch" % k)
+            arr[k] = _Image(X.data_ptr(), C.data_ptr() if C is not None else None, H, W, ld, r)
+        self._stream()
+        self._check(_lib.hasf_filter_batch(self._h, arr, len(items)))
+        return [X for X, _, _ in items]
