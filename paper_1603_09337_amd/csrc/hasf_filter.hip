@@ -34,7 +34,7 @@ __device__ __forceinline__ uint64_t feat_word(const Img<LDS>& g, int row, int w,
 {
     if (row < 0 || row >= g.H || w < 0 || w >= g.WW)
         return frame ? ~0ull : 0ull;
-    const uint64_t s = g.S[row * g.WW + w];
+    const uint64_t s = g.S[g.at(row, w)];
     return frame ? ~s : s;  // bits past W: ~0 = outside (frame) / 0 (no frame)
 }
 
@@ -78,8 +78,7 @@ __device__ __attribute__((noinline)) void stage(const ImgDesc* __restrict__ dp, 
         uint64_t base = 0;
         int row = 0, w = 0;
         if (q < g.NWD) {
-            row = q / g.WW;
-            w = q - row * g.WW;
+            g.rowcol(q, row, w);
             const uint64_t s = g.S[q];
             const uint64_t valid = (w == g.WW - 1) ? g.lastmask : ~0ull;
             switch (mode) {
@@ -182,9 +181,13 @@ __device__ __attribute__((noinline)) void level_loop(const ImgDesc* __restrict__
         if (c == 0)
             continue;
         const size_t e0 = (size_t)k * g.NWD;
-        for (unsigned t = threadIdx.x; t < c; t += BLOCK)
-            __hip_atomic_fetch_or(g.M + g.eidx[e0 + t], (uint64_t)g.emsk[e0 + t], __ATOMIC_RELAXED,
+        for (unsigned t = threadIdx.x; t < c; t += BLOCK) {
+            const uint32_t q = g.eidx[e0 + t];
+            __hip_atomic_fetch_or(g.M + q, (uint64_t)g.emsk[e0 + t], __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            g.D0[q] = 1;
+            g.D1[q] = 1;
+        }
         __syncthreads();
         run_rounds(g, thin);
     }
@@ -193,8 +196,11 @@ __device__ __attribute__((noinline)) void level_loop(const ImgDesc* __restrict__
 template <bool LDS>
 __device__ void clear_phase(const Img<LDS>& g, lds_u32* cnt, int nlev)
 {
-    for (int q = threadIdx.x; q < g.NWD; q += BLOCK)
+    for (int q = threadIdx.x; q < g.NWD; q += BLOCK) {
         g.M[q] = 0;
+        g.D0[q] = 0;
+        g.D1[q] = 0;
+    }
     for (int k = threadIdx.x; k < nlev; k += BLOCK)
         cnt[k] = 0;
 }
@@ -235,7 +241,7 @@ __device__ __attribute__((noinline)) void run_image(const ImgDesc* __restrict__ 
 }  // namespace
 
 // Each workgroup claims images in queue order until the queue is empty.
-__global__ __launch_bounds__(BLOCK) void hasf_filter_kernel(const ImgDesc* __restrict__ desc, int n,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void hasf_filter_kernel(const ImgDesc* __restrict__ desc, int n,
                                                             int* __restrict__ next)
 {
     extern __shared__ uint64_t smem[];

@@ -49,10 +49,10 @@ __device__ unsigned block_exclusive_scan(unsigned v, unsigned* out_prefix, unsig
     return total;
 }
 
-template <typename PP>
-__device__ __forceinline__ bool bit_at(PP plane, int WW, int i, int j)
+template <bool LDS, typename PP>
+__device__ __forceinline__ bool bit_at(const Img<LDS>& g, PP plane, int i, int j)
 {
-    return (plane[i * WW + (j >> 6)] >> (j & 63)) & 1ull;
+    return (plane[g.at(i, j >> 6)] >> (j & 63)) & 1ull;
 }
 
 template <bool LDS>
@@ -64,15 +64,19 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     g.W = a.W;
     g.WW = (a.W + 63) >> 6;
     g.NWD = g.H * g.WW;
+    g.E = ((g.H + 1) >> 1) * g.WW;
     g.lastmask = (a.W & 63) ? ((1ull << (a.W & 63)) - 1ull) : ~0ull;
     glb_u64* gp = (glb_u64*)a.planes;
     if constexpr (LDS) {
         g.S = (lds_u64*)smem;
         g.M = (lds_u64*)smem + g.NWD;
+        g.D0 = (lds_u8*)((lds_u64*)smem + 2 * (size_t)g.NWD);
     } else {
         g.S = gp;
         g.M = gp + g.NWD;
+        g.D0 = (glb_u8*)(gp + 3 * (size_t)g.NWD);
     }
+    g.D1 = g.D0 + g.NWD;
     glb_u64* Bp = gp + 2 * (size_t)g.NWD;
     g.A = Bp;
     g.K = Bp;
@@ -89,6 +93,7 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
         gb.W = g.W;
         gb.WW = g.WW;
         gb.NWD = g.NWD;
+        gb.E = g.E;
         gb.S = Bp;
         gb.hasK = false;
         if (a.B)
@@ -97,8 +102,11 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
             for (int q = threadIdx.x; q < g.NWD; q += BLOCK)
                 Bp[q] = 0;
     }
-    for (int q = threadIdx.x; q < g.NWD; q += BLOCK)
+    for (int q = threadIdx.x; q < g.NWD; q += BLOCK) {
         g.M[q] = 0;
+        g.D0[q] = 0;
+        g.D1[q] = 0;
+    }
     glb_u64* bm = (glb_u64*)a.bitmap;
     for (unsigned long long q = threadIdx.x; q < a.nbw; q += BLOCK)
         bm[q] = 0;
@@ -107,7 +115,7 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     // mark the priority values of the candidates
     for (int p = threadIdx.x; p < N; p += BLOCK) {
         const int i = p / a.W, j = p - i * a.W;
-        const bool s = bit_at(g.S, g.WW, i, j), b = bit_at(Bp, g.WW, i, j);
+        const bool s = bit_at(g, g.S, i, j), b = bit_at(g, Bp, i, j);
         if (a.thin ? (s && !b) : (!s && b)) {
             const uint32_t v = a.P[(size_t)i * a.W + j];
             if (v != 0xFFFFFFFFu)
@@ -138,7 +146,7 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     // count candidates per level
     for (int p = threadIdx.x; p < N; p += BLOCK) {
         const int i = p / a.W, j = p - i * a.W;
-        const bool s = bit_at(g.S, g.WW, i, j), b = bit_at(Bp, g.WW, i, j);
+        const bool s = bit_at(g, g.S, i, j), b = bit_at(g, Bp, i, j);
         if (a.thin ? (s && !b) : (!s && b)) {
             const uint32_t v = a.P[(size_t)i * a.W + j];
             if (v != 0xFFFFFFFFu) {
@@ -169,7 +177,7 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     g32* ent = (g32*)a.ent;
     for (int p = threadIdx.x; p < N; p += BLOCK) {
         const int i = p / a.W, j = p - i * a.W;
-        const bool s = bit_at(g.S, g.WW, i, j), b = bit_at(Bp, g.WW, i, j);
+        const bool s = bit_at(g, g.S, i, j), b = bit_at(g, Bp, i, j);
         if (a.thin ? (s && !b) : (!s && b)) {
             const uint32_t v = a.P[(size_t)i * a.W + j];
             if (v != 0xFFFFFFFFu) {
@@ -189,8 +197,10 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
         for (unsigned t = e0 + threadIdx.x; t < e1; t += BLOCK) {
             const unsigned p = ent[t];
             const int i = (int)(p / (unsigned)a.W), j = (int)(p - (unsigned)i * (unsigned)a.W);
-            __hip_atomic_fetch_or(g.M + (i * g.WW + (j >> 6)), 1ull << (j & 63), __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+            const int q = g.at(i, j >> 6);
+            __hip_atomic_fetch_or(g.M + q, 1ull << (j & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            g.D0[q] = 1;
+            g.D1[q] = 1;
         }
         __syncthreads();
         run_rounds(g, a.thin != 0);

@@ -161,6 +161,21 @@ class Context:
         self._check(_lib.hasf_filter(self._h, _ptr(X), _ptr(C), H, W, ld, r))
         return X
 
+    def plan_batch(self, items):
+        """Prepare the descriptor array of a batch once (the tensors must stay alive)."""
+        arr = (_Image * max(1, len(items)))()
+        for k, (X, C, r) in enumerate(items):
+            H, W, ld = _img(X, "X[%d]" % k)
+            if C is not None and (C.shape != X.shape or C.stride(0) != ld):
+                raise ValueError("C[%d] must match X's shape and pitch" % k)
+            arr[k] = _Image(X.data_ptr(), C.data_ptr() if C is not None else None, H, W, ld, r)
+        return (arr, len(items), list(items))
+
+    def run_plan(self, plan):
+        arr, n, _ = plan
+        self._stream()
+        self._check(_lib.hasf_filter_batch(self._h, arr, n))
+
     def filter_batch(self, items):
         """items: sequence of (X, C or None, r)."""
         arr = (_Image * max(1, len(items)))()
