@@ -305,7 +305,8 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
         const size_t WW = (size_t)(im.W + 63) / 64;
         const size_t NWD = (size_t)im.H * WW;
         // LDS: S and M planes (8 B/word each) and the two flag bytes per word
-        const bool lds = align256(2 * NWD * 8 + 2 * NWD) <= lds_cap;
+        const size_t sb = align256(state_bytes(im.H, im.W));
+        const bool lds = sb <= lds_cap;
         const size_t nlev = (size_t)std::max(1, levels_host(im.r));
         ImgDesc& d = desc[q];
         d.X = im.X;
@@ -316,10 +317,11 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
         d.r = im.r;
         d.lds = lds ? 1 : 0;
         if (lds)
-            lds_need = std::max(lds_need, align256(2 * NWD * 8 + 2 * NWD));
+            lds_need = std::max(lds_need, sb);
         // offsets for now; rebased after allocation
         d.gplanes = (uint64_t*)bytes;
-        bytes += align256((lds ? 2 : 4) * NWD * 8 + (lds ? 0 : 2 * NWD));
+        // global: [state (unless in LDS) | A | K]
+        bytes += align256((lds ? 0 : sb) + 2 * NWD * 8);
         d.ent_idx = (uint32_t*)bytes;
         bytes += align256(nlev * NWD * 4);
         d.ent_msk = (uint64_t*)bytes;
@@ -405,11 +407,12 @@ hasf_status run_topo(hasf_ctx* ctx, uint8_t* X, const uint8_t* B, int H, int W, 
     }
     const unsigned long long nbw = vmax / 64 + 1;
     const size_t lds_cap = std::min(ctx->lds_per_block, (size_t)160 * 1024) - 4096;
-    const bool lds = align256(2 * NWD * 8 + 2 * NWD) <= lds_cap;
+    const size_t sb = align256(state_bytes(H, W));
+    const bool lds = sb <= lds_cap;
     size_t off = 0;
     const size_t oP = off; off += align256(N * 4);
     const size_t oE = off; off += align256(edt_scratch_bytes(H, W));
-    const size_t oPl = off; off += align256(3 * NWD * 8 + 2 * NWD);
+    const size_t oPl = off; off += align256((lds ? 0 : sb) + NWD * 8);  // [state | B bits]
     const size_t oBm = off; off += align256(nbw * 8);
     const size_t oRb = off; off += align256(nbw * 4);
     const size_t oH = off; off += align256((N + 1) * 4);
@@ -438,7 +441,7 @@ hasf_status run_topo(hasf_ctx* ctx, uint8_t* X, const uint8_t* B, int H, int W, 
     a.hist = (uint32_t*)(base + oH);
     a.ent = (uint32_t*)(base + oEn);
     a.nbw = nbw;
-    e = launch_topo(a, lds ? align256(2 * NWD * 8 + 2 * NWD) : 0, ctx->stream);
+    e = launch_topo(a, lds ? sb : 0, ctx->stream);
     if (e != hipSuccess)
         return dev_fail(ctx, e, "topo launch");
     return HASF_OK;

@@ -100,6 +100,19 @@ static_assert(make_ball_pairs(HASF_R_MAX).n <= 256, "ball offsets");
 static_assert(level_count(HASF_R_MAX) <= 128, "level counters");
 constexpr int HASF_LEVELS_MAX = level_count(HASF_R_MAX);
 
+// Bytes of the state kept per image (LDS when it fits, else global memory):
+//   S  the current set as four subfield sub-images: sub-image (si, sj) holds
+//      the pixels (2r + si, 2c + sj), 32 columns c per 32-bit word;
+//   M  the activated candidates, same layout; its memory also holds R, the
+//      row-major view of S (64 columns per 64-bit word) that the distance
+//      stages read, while no candidate is active;
+//   D  one byte per sub-image word: the word must be re-tested.
+__host__ __device__ inline size_t state_bytes(int H, int W)
+{
+    const size_t WW = (size_t)(W + 63) / 64, HH = (size_t)(H + 1) / 2;
+    return 36 * HH * WW;
+}
+
 // ---------------------------------------------------------------------------
 // Per-image descriptor used by the persistent filter kernel.
 // ---------------------------------------------------------------------------

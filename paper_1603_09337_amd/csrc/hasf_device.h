@@ -1,5 +1,5 @@
-// Device code shared by the libhasf kernels: bit-packed planes, packing of
-// byte images, and the subfield rounds of thinning / thickening.
+// Device code shared by the libhasf kernels: the bit-packed state of an image,
+// packing of byte images, and the subfield rounds of thinning / thickening.
 #pragma once
 
 #include <type_traits>
@@ -9,15 +9,13 @@
 namespace hasf_dev {
 
 constexpr int BLOCK = 512;
-constexpr uint64_t EVEN_COLS = 0x5555555555555555ull;
-constexpr uint64_t ODD_COLS = 0xAAAAAAAAAAAAAAAAull;
 
 // explicit address spaces keep LDS accesses on ds_* and global ones on
 // global_* instructions across non-inlined calls
 typedef __attribute__((address_space(3))) uint64_t lds_u64;
 typedef __attribute__((address_space(1))) uint64_t glb_u64;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
 typedef __attribute__((address_space(1))) uint32_t glb_u32;
-typedef __attribute__((address_space(3))) unsigned lds_u32;
 typedef __attribute__((address_space(3))) uint8_t lds_u8;
 typedef __attribute__((address_space(1))) uint8_t glb_u8;
 
@@ -28,70 +26,63 @@ enum StageMode {
     HF_THIN = 3      // features = complement u outside; base = S \ A
 };
 
+// bits 0, 2, 4, ... of x -> bits 0..31
+__device__ __forceinline__ uint32_t even_bits(uint64_t x)
+{
+    x &= 0x5555555555555555ull;
+    x = (x | (x >> 1)) & 0x3333333333333333ull;
+    x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x >> 16)) & 0x00000000FFFFFFFFull;
+    return (uint32_t)x;
+}
+
+// bit t of v -> bit 2t
+__device__ __forceinline__ uint64_t spread_bits(uint32_t v)
+{
+    uint64_t x = v;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
 template <bool LDS>
 struct Img {
-    using P = typename std::conditional<LDS, lds_u64*, glb_u64*>::type;
-    using PD = typename std::conditional<LDS, lds_u8*, glb_u8*>::type;
-    P S;          // current set
-    P M;          // activated candidates of the running phase
-    PD D0, D1;    // per word: must be re-tested in the even / odd column subfield
-    glb_u64* A;   // set saved before the phase
-    glb_u64* K;   // constraint set
+    using P64 = typename std::conditional<LDS, lds_u64*, glb_u64*>::type;
+    using P32 = typename std::conditional<LDS, lds_u32*, glb_u32*>::type;
+    using P8 = typename std::conditional<LDS, lds_u8*, glb_u8*>::type;
+    P64 R;        // row-major view of the current set (distance stages)
+    P32 S;        // current set, four sub-images
+    P32 M;        // activated candidates, four sub-images (shares memory with R)
+    P8 D;         // per sub-image word: must be re-tested
+    glb_u64* A;   // set saved before the phase (row-major)
+    glb_u64* K;   // constraint set (row-major)
     glb_u32* eidx;
     glb_u64* emsk;
-    int H, W, WW, NWD;
-    int E;              // first word of the odd-row half of a plane
+    int H, W, WW, NWD, HH, SUB;
     uint64_t lastmask;  // valid bits of the last word of a row
     bool hasK;
 
-    // Planes are stored split by row parity: the even rows first, then the odd
-    // rows, so that the words of one subfield pass and of its neighbouring
-    // rows are contiguous in memory (conflict-free LDS access per wave).
-    __device__ __forceinline__ int at(int row, int w) const
-    {
-        return ((row & 1) ? E : 0) + (row >> 1) * WW + w;
-    }
-    // row and word of memory index q
-    __device__ __forceinline__ void rowcol(int q, int& row, int& w) const
-    {
-        const bool odd = q >= E;
-        const int r2 = odd ? q - E : q;
-        const int rr = r2 / WW;
-        w = r2 - rr * WW;
-        row = 2 * rr + (odd ? 1 : 0);
-    }
+    __device__ __forceinline__ int sub(int si, int sj) const { return (si * 2 + sj) * SUB; }
 };
 
+// state at `base` (LDS or global), laid out as S | M (= R) | D
 template <bool LDS>
-__device__ __forceinline__ Img<LDS> make_img(const ImgDesc* __restrict__ dp, uint64_t* smem)
+__device__ __forceinline__ void bind_state(Img<LDS>& g, void* base)
 {
-    Img<LDS> g;
-    g.H = dp->H;
-    g.W = dp->W;
     g.WW = (g.W + 63) >> 6;
     g.NWD = g.H * g.WW;
-    g.E = ((g.H + 1) >> 1) * g.WW;
+    g.HH = (g.H + 1) >> 1;
+    g.SUB = g.HH * g.WW;
     g.lastmask = (g.W & 63) ? ((1ull << (g.W & 63)) - 1ull) : ~0ull;
-    glb_u64* gp = (glb_u64*)dp->gplanes;
-    if constexpr (LDS) {
-        g.S = (lds_u64*)smem;
-        g.M = (lds_u64*)smem + g.NWD;
-        g.D0 = (lds_u8*)((lds_u64*)smem + 2 * (size_t)g.NWD);
-        g.D1 = g.D0 + g.NWD;
-        g.A = gp;
-        g.K = gp + g.NWD;
-    } else {
-        g.S = gp;
-        g.M = gp + g.NWD;
-        g.A = gp + 2 * (size_t)g.NWD;
-        g.K = gp + 3 * (size_t)g.NWD;
-        g.D0 = (glb_u8*)(gp + 4 * (size_t)g.NWD);
-        g.D1 = g.D0 + g.NWD;
-    }
-    g.hasK = dp->C != nullptr;
-    g.eidx = (glb_u32*)dp->ent_idx;
-    g.emsk = (glb_u64*)dp->ent_msk;
-    return g;
+    g.S = (typename Img<LDS>::P32)base;
+    g.M = g.S + 4 * (size_t)g.SUB;
+    g.R = (typename Img<LDS>::P64)g.M;
+    g.D = (typename Img<LDS>::P8)(g.M + 4 * (size_t)g.SUB);
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt()
@@ -115,20 +106,22 @@ __device__ __forceinline__ uint32_t expand4(uint32_t nib)
     return (nib * 0x00204081u) & 0x01010101u;
 }
 
-// Pack nonzero bytes of X (and C) into words: one thread per word.
-template <bool LDS>
-__device__ void pack_image(const uint8_t* __restrict__ X, const uint8_t* __restrict__ C, long long ld,
-                           const Img<LDS>& g)
+// Row-major 64-bit words of the nonzero bytes of X (and of C n X into K when
+// K is given): one thread per word.
+template <typename PR>
+__device__ void pack_rows(const uint8_t* __restrict__ X, const uint8_t* __restrict__ C, long long ld, int H,
+                          int W, PR R, glb_u64* K)
 {
+    const int WW = (W + 63) >> 6, NWD = H * WW;
     const bool vec_ok = ((((uintptr_t)X) | (C ? (uintptr_t)C : 0) | (uintptr_t)ld) & 15) == 0;
-    for (int q = threadIdx.x; q < g.NWD; q += BLOCK) {
-        int row, w;
-        g.rowcol(q, row, w);
+    for (int q = threadIdx.x; q < NWD; q += BLOCK) {
+        const int row = q / WW;
+        const int w = q - row * WW;
         const int c0 = w * 64;
         const uint8_t* xr = X + (long long)row * ld + c0;
         const uint8_t* cr = C ? C + (long long)row * ld + c0 : nullptr;
         uint64_t m = 0, k = 0;
-        if (vec_ok && c0 + 64 <= g.W) {
+        if (vec_ok && c0 + 64 <= W) {
             const uint4* xp = reinterpret_cast<const uint4*>(xr);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -146,30 +139,31 @@ __device__ void pack_image(const uint8_t* __restrict__ X, const uint8_t* __restr
                 }
             }
         } else {
-            const int n = min(64, g.W - c0);
+            const int n = min(64, W - c0);
             for (int j = 0; j < n; ++j) {
                 m |= (uint64_t)(xr[j] != 0) << j;
                 if (cr)
                     k |= (uint64_t)(cr[j] != 0) << j;
             }
         }
-        g.S[q] = m;
-        if (g.hasK)
-            g.K[q] = k & m;
+        R[q] = m;
+        if (K)
+            K[q] = k & m;
     }
 }
 
-template <bool LDS>
-__device__ void unpack_image(uint8_t* __restrict__ X, long long ld, const Img<LDS>& g)
+template <typename PR>
+__device__ void unpack_rows(uint8_t* __restrict__ X, long long ld, int H, int W, PR R)
 {
+    const int WW = (W + 63) >> 6, NWD = H * WW;
     const bool vec_ok = ((((uintptr_t)X) | (uintptr_t)ld) & 15) == 0;
-    for (int q = threadIdx.x; q < g.NWD; q += BLOCK) {
-        int row, w;
-        g.rowcol(q, row, w);
+    for (int q = threadIdx.x; q < NWD; q += BLOCK) {
+        const int row = q / WW;
+        const int w = q - row * WW;
         const int c0 = w * 64;
         uint8_t* xr = X + (long long)row * ld + c0;
-        const uint64_t m = g.S[q];
-        if (vec_ok && c0 + 64 <= g.W) {
+        const uint64_t m = R[q];
+        if (vec_ok && c0 + 64 <= W) {
             uint4* xp = reinterpret_cast<uint4*>(xr);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -182,42 +176,101 @@ __device__ void unpack_image(uint8_t* __restrict__ X, long long ld, const Img<LD
                 xp[j] = v;
             }
         } else {
-            const int n = min(64, g.W - c0);
+            const int n = min(64, W - c0);
             for (int j = 0; j < n; ++j)
                 xr[j] = (uint8_t)((m >> j) & 1u);
         }
     }
 }
 
-// word (row, w) of a plane, 0 outside the window
-template <bool LDS, typename PP>
-__device__ __forceinline__ uint64_t ld_word(const Img<LDS>& g, PP p, int row, int w)
+// R -> S (the four sub-images); S -> R
+template <bool LDS>
+__device__ void rows_to_sub(const Img<LDS>& g)
 {
-    if (row < 0 || row >= g.H || w < 0 || w >= g.WW)
-        return 0;
-    return p[g.at(row, w)];
+    for (int q = threadIdx.x; q < g.NWD; q += BLOCK) {
+        const int row = q / g.WW;
+        const int w = q - row * g.WW;
+        const uint64_t v = g.R[q];
+        const int o = (row >> 1) * g.WW + w;
+        g.S[g.sub(row & 1, 0) + o] = even_bits(v);
+        g.S[g.sub(row & 1, 1) + o] = even_bits(v >> 1);
+    }
+}
+
+template <bool LDS>
+__device__ void sub_to_rows(const Img<LDS>& g)
+{
+    for (int q = threadIdx.x; q < g.NWD; q += BLOCK) {
+        const int row = q / g.WW;
+        const int w = q - row * g.WW;
+        const int o = (row >> 1) * g.WW + w;
+        g.R[q] = spread_bits(g.S[g.sub(row & 1, 0) + o]) | (spread_bits(g.S[g.sub(row & 1, 1) + o]) << 1);
+    }
+}
+
+// no candidate active, no word flagged (destroys R)
+template <bool LDS>
+__device__ void clear_candidates(const Img<LDS>& g)
+{
+    for (int q = threadIdx.x; q < 4 * g.SUB; q += BLOCK) {
+        g.M[q] = 0;
+        g.D[q] = 0;
+    }
+}
+
+// activate the candidate bits `m` of row-major word (row, w)
+template <bool LDS>
+__device__ __forceinline__ void activate_row_word(const Img<LDS>& g, int row, int w, uint64_t m)
+{
+    const int o = (row >> 1) * g.WW + w;
+    const uint32_t e = even_bits(m), od = even_bits(m >> 1);
+    if (e) {
+        const int q = g.sub(row & 1, 0) + o;
+        __hip_atomic_fetch_or(g.M + q, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        g.D[q] = 1;
+    }
+    if (od) {
+        const int q = g.sub(row & 1, 1) + o;
+        __hip_atomic_fetch_or(g.M + q, od, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        g.D[q] = 1;
+    }
+}
+
+// activate pixel (i, j)
+template <bool LDS>
+__device__ __forceinline__ void activate_pixel(const Img<LDS>& g, int i, int j)
+{
+    const int c = j >> 1;
+    const int q = g.sub(i & 1, j & 1) + (i >> 1) * g.WW + (c >> 5);
+    __hip_atomic_fetch_or(g.M + q, 1u << (c & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    g.D[q] = 1;
 }
 
 // Rounds of the four subfield passes (even,even) (even,odd) (odd,even)
 // (odd,odd) until a round changes nothing. A pass tests, on the state left by
 // the previous pass, the activated candidates of its subfield and flips the
 // simple ones (thinning deletes, thickening adds). Two points of one subfield
-// are never 8-adjacent, so a pass is a pure data-parallel map.
+// are never 8-adjacent, so a pass is a pure data-parallel map: it writes only
+// its own sub-image and reads the other three, whose pixels are its points'
+// neighbours (E/W: same rows, other column parity; N/S: other row parity,
+// same columns; diagonals: the fourth sub-image).
 //
-// A word is only re-tested when something that its test reads has changed
-// since its last test: D0/D1 flag the words whose even / odd columns must be
-// tested, set by a new activation in the word and by a change in its 3x3 word
-// neighbourhood. An unflagged word would test exactly as before (no simple
+// A word is only re-tested when something its test reads has changed since
+// its last test: D flags a word on a new activation in it and on a change in
+// a word it reads. An unflagged word would test exactly as before (no simple
 // candidate), so skipping it leaves the schedule and its result unchanged.
+// A pass only clears the flags of its own sub-image and only sets flags of
+// the other three, so flags need no atomics.
 template <bool LDS>
 __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin)
 {
-    const int rstep = BLOCK / g.WW;  // rows covered per sweep step
-    const int my_r = threadIdx.x / g.WW;
-    const int my_w = threadIdx.x - my_r * g.WW;
+    const int WW = g.WW;
+    const int rstep = BLOCK / WW;  // rows covered per sweep step
+    const int my_r = threadIdx.x / WW;
+    const int my_w = threadIdx.x - my_r * WW;
     const bool active = my_r < rstep;
-    const uint64_t flip = thin ? 0ull : ~0ull;  // live = M & (S ^ flip)
-    const bool has_l = my_w > 0, has_r = my_w + 1 < g.WW;
+    const uint32_t flip = thin ? 0u : ~0u;  // live = M & (S ^ flip)
+    const bool hasL = my_w > 0, hasR = my_w + 1 < WW;
     // "something changed in round n" lives in chg[n & 1]: written by any
     // changer, read by all after the round's last barrier, and cleared for
     // round n + 1 after the first barrier of round n (when every thread has
@@ -233,75 +286,85 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int si = s >> 1, sj = s & 1;
-            const uint64_t cm = sj ? ODD_COLS : EVEN_COLS;
-            auto Dself = sj ? g.D1 : g.D0;
-            auto Doth = sj ? g.D0 : g.D1;
+            const int so = 1 - si, co = 1 - sj;
+            const auto Ss = g.S + g.sub(si, sj);
+            const auto Ms = g.M + g.sub(si, sj);
+            const auto Ds = g.D + g.sub(si, sj);
+            const auto Sx = g.S + g.sub(si, co);   // E, W
+            const auto Sy = g.S + g.sub(so, sj);   // N, S
+            const auto Sxy = g.S + g.sub(so, co);  // diagonals
+            const auto Dx = g.D + g.sub(si, co);
+            const auto Dy = g.D + g.sub(so, sj);
+            const auto Dxy = g.D + g.sub(so, co);
+            const int rows = (g.H - si + 1) >> 1;
             if (active) {
-                for (int rr = my_r;; rr += rstep) {
-                    const int row = si + 2 * rr;
-                    if (row >= g.H)
-                        break;
-                    const int idx = (si ? g.E : 0) + rr * g.WW + my_w;
-                    if (!Dself[idx])
+                for (int rr = my_r; rr < rows; rr += rstep) {
+                    const int idx = rr * WW + my_w;
+                    if (!Ds[idx])
                         continue;
-                    Dself[idx] = 0;
-                    const uint64_t sc = g.S[idx];
-                    const uint64_t live = g.M[idx] & cm & (sc ^ flip);
+                    Ds[idx] = 0;
+                    const uint32_t sc = Ss[idx];
+                    const uint32_t live = Ms[idx] & (sc ^ flip);
                     if (!live)
                         continue;
-                    // rows row-1 and row+1 live in the other parity half
-                    const bool has_u = row > 0, has_d = row + 1 < g.H;
-                    const int iu = (si ? 0 : g.E) + (rr - (si ? 0 : 1)) * g.WW + my_w;
-                    const int id = (si ? 0 : g.E) + (rr + (si ? 1 : 0)) * g.WW + my_w;
-                    const uint64_t u = has_u ? g.S[iu] : 0;
-                    const uint64_t ul = has_u && has_l ? g.S[iu - 1] : 0;
-                    const uint64_t ur = has_u && has_r ? g.S[iu + 1] : 0;
-                    const uint64_t cl = has_l ? g.S[idx - 1] : 0;
-                    const uint64_t cr = has_r ? g.S[idx + 1] : 0;
-                    const uint64_t d = has_d ? g.S[id] : 0;
-                    const uint64_t dl = has_d && has_l ? g.S[id - 1] : 0;
-                    const uint64_t dr = has_d && has_r ? g.S[id + 1] : 0;
-                    // bit p of E = column p+1, of W = column p-1
-                    const uint64_t xE = (sc >> 1) | (cr << 63);
-                    const uint64_t xW = (sc << 1) | (cl >> 63);
-                    const uint64_t xNE = (u >> 1) | (ur << 63);
-                    const uint64_t xNW = (u << 1) | (ul >> 63);
-                    const uint64_t xSE = (d >> 1) | (dr << 63);
-                    const uint64_t xSW = (d << 1) | (dl >> 63);
-                    const uint64_t del = live & simple_bits<uint64_t>(xE, xNE, u, xNW, xW, xSW, d, xSE);
+                    const int row = 2 * rr + si;
+                    const bool hasN = row > 0, hasS = row + 1 < g.H;
+                    const int iN = (si ? rr : rr - 1) * WW + my_w;  // row - 1 in the other parity
+                    const int iS = (si ? rr + 1 : rr) * WW + my_w;  // row + 1
+                    const uint32_t xc = Sx[idx];
+                    const uint32_t xl = hasL ? Sx[idx - 1] : 0u;
+                    const uint32_t xr = hasR ? Sx[idx + 1] : 0u;
+                    const uint32_t n = hasN ? Sy[iN] : 0u;
+                    const uint32_t sv = hasS ? Sy[iS] : 0u;
+                    const uint32_t nc = hasN ? Sxy[iN] : 0u;
+                    const uint32_t nl = hasN && hasL ? Sxy[iN - 1] : 0u;
+                    const uint32_t nr = hasN && hasR ? Sxy[iN + 1] : 0u;
+                    const uint32_t dc = hasS ? Sxy[iS] : 0u;
+                    const uint32_t dl = hasS && hasL ? Sxy[iS - 1] : 0u;
+                    const uint32_t dr = hasS && hasR ? Sxy[iS + 1] : 0u;
+                    // column c of this sub-image is image column 2c + sj; its
+                    // east neighbour is column c (sj = 0) or c + 1 (sj = 1) of
+                    // the other column parity, its west one c - 1 or c
+                    uint32_t e, w, ne, nw, se, sw;
+                    if (sj == 0) {
+                        e = xc;
+                        w = (xc << 1) | (xl >> 31);
+                        ne = nc;
+                        nw = (nc << 1) | (nl >> 31);
+                        se = dc;
+                        sw = (dc << 1) | (dl >> 31);
+                    } else {
+                        e = (xc >> 1) | (xr << 31);
+                        w = xc;
+                        ne = (nc >> 1) | (nr << 31);
+                        nw = nc;
+                        se = (dc >> 1) | (dr << 31);
+                        sw = dc;
+                    }
+                    const uint32_t del = live & simple_bits<uint32_t>(e, ne, n, nw, w, sw, sv, se);
                     if (del) {
-                        g.S[idx] = sc ^ del;  // thin clears, thicken sets the bits of del
+                        Ss[idx] = sc ^ del;  // thin clears, thicken sets the bits of del
                         changed = 1;
-                        // the other column parity of this word and of the words
-                        // beside it; both parities of the three words above and below
-                        Doth[idx] = 1;
-                        if (has_l)
-                            Doth[idx - 1] = 1;
-                        if (has_r)
-                            Doth[idx + 1] = 1;
-                        if (has_u) {
-                            g.D0[iu] = 1;
-                            g.D1[iu] = 1;
-                            if (has_l) {
-                                g.D0[iu - 1] = 1;
-                                g.D1[iu - 1] = 1;
-                            }
-                            if (has_r) {
-                                g.D0[iu + 1] = 1;
-                                g.D1[iu + 1] = 1;
-                            }
+                        Dx[idx] = 1;
+                        if (hasL)
+                            Dx[idx - 1] = 1;
+                        if (hasR)
+                            Dx[idx + 1] = 1;
+                        if (hasN) {
+                            Dy[iN] = 1;
+                            Dxy[iN] = 1;
+                            if (hasL)
+                                Dxy[iN - 1] = 1;
+                            if (hasR)
+                                Dxy[iN + 1] = 1;
                         }
-                        if (has_d) {
-                            g.D0[id] = 1;
-                            g.D1[id] = 1;
-                            if (has_l) {
-                                g.D0[id - 1] = 1;
-                                g.D1[id - 1] = 1;
-                            }
-                            if (has_r) {
-                                g.D0[id + 1] = 1;
-                                g.D1[id + 1] = 1;
-                            }
+                        if (hasS) {
+                            Dy[iS] = 1;
+                            Dxy[iS] = 1;
+                            if (hasL)
+                                Dxy[iS - 1] = 1;
+                            if (hasR)
+                                Dxy[iS + 1] = 1;
                         }
                     }
                 }

@@ -34,14 +34,39 @@ __device__ __forceinline__ uint64_t feat_word(const Img<LDS>& g, int row, int w,
 {
     if (row < 0 || row >= g.H || w < 0 || w >= g.WW)
         return frame ? ~0ull : 0ull;
-    const uint64_t s = g.S[g.at(row, w)];
+    const uint64_t s = g.R[row * g.WW + w];
     return frame ? ~s : s;  // bits past W: ~0 = outside (frame) / 0 (no frame)
 }
 
-// Append `acc` (candidate bits of word q at level `rank`) to the level's entry
-// list, one LDS atomic per wave.
 template <bool LDS>
-__device__ __forceinline__ void flush_level(const Img<LDS>& g, lds_u32* cnt, int rank, int q, uint64_t acc)
+__device__ __forceinline__ Img<LDS> make_img(const ImgDesc* __restrict__ dp, uint64_t* smem)
+{
+    Img<LDS> g;
+    g.H = dp->H;
+    g.W = dp->W;
+    glb_u64* gp = (glb_u64*)dp->gplanes;
+    const size_t NWD = (size_t)g.H * ((g.W + 63) >> 6);
+    if constexpr (LDS) {
+        bind_state(g, (void*)smem);
+        g.A = gp;
+        g.K = gp + NWD;
+    } else {
+        bind_state(g, (void*)gp);
+        const size_t sb = (state_bytes(g.H, g.W) + 255) / 256 * 256;
+        g.A = (glb_u64*)((glb_u8*)gp + sb);
+        g.K = g.A + NWD;
+    }
+    g.hasK = dp->C != nullptr;
+    g.eidx = (glb_u32*)dp->ent_idx;
+    g.emsk = (glb_u64*)dp->ent_msk;
+    return g;
+}
+
+// Append `acc` (candidate bits of row-major word (row, w) at level `rank`) to
+// the level's entry list, one LDS atomic per wave.
+template <bool LDS>
+__device__ __forceinline__ void flush_level(const Img<LDS>& g, lds_u32* cnt, int rank, int row, int w,
+                                            uint64_t acc)
 {
     const uint64_t pred = __ballot(acc != 0);
     if (pred == 0)
@@ -56,7 +81,7 @@ __device__ __forceinline__ void flush_level(const Img<LDS>& g, lds_u32* cnt, int
     if (acc) {
         const unsigned slot = base + (unsigned)__popcll(pred & lanemask_lt());
         const size_t e = (size_t)rank * g.NWD + slot;
-        g.eidx[e] = (uint32_t)q;
+        g.eidx[e] = ((uint32_t)row << 10) | (uint32_t)w;
         g.emsk[e] = acc;
     }
 }
@@ -78,8 +103,9 @@ __device__ __attribute__((noinline)) void stage(const ImgDesc* __restrict__ dp, 
         uint64_t base = 0;
         int row = 0, w = 0;
         if (q < g.NWD) {
-            g.rowcol(q, row, w);
-            const uint64_t s = g.S[q];
+            row = q / g.WW;
+            w = q - row * g.WW;
+            const uint64_t s = g.R[q];
             const uint64_t valid = (w == g.WW - 1) ? g.lastmask : ~0ull;
             switch (mode) {
             case HC_THIN:
@@ -139,7 +165,7 @@ __device__ __attribute__((noinline)) void stage(const ImgDesc* __restrict__ dp, 
             acc |= x & ~cov & base;
             cov |= x;
             if (k == P.n - 1 || P.v[k + 1] != P.v[k]) {
-                flush_level(g, cnt, P.rank[k], q, acc);
+                flush_level(g, cnt, P.rank[k], row, w, acc);
                 acc = 0;
             }
         }
@@ -182,27 +208,13 @@ __device__ __attribute__((noinline)) void level_loop(const ImgDesc* __restrict__
             continue;
         const size_t e0 = (size_t)k * g.NWD;
         for (unsigned t = threadIdx.x; t < c; t += BLOCK) {
-            const uint32_t q = g.eidx[e0 + t];
-            __hip_atomic_fetch_or(g.M + q, (uint64_t)g.emsk[e0 + t], __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_WORKGROUP);
-            g.D0[q] = 1;
-            g.D1[q] = 1;
+            const uint32_t p = g.eidx[e0 + t];
+            activate_row_word(g, (int)(p >> 10), (int)(p & 1023u), (uint64_t)g.emsk[e0 + t]);
         }
         __syncthreads();
         run_rounds(g, thin);
     }
-}
-
-template <bool LDS>
-__device__ void clear_phase(const Img<LDS>& g, lds_u32* cnt, int nlev)
-{
-    for (int q = threadIdx.x; q < g.NWD; q += BLOCK) {
-        g.M[q] = 0;
-        g.D0[q] = 0;
-        g.D1[q] = 0;
-    }
-    for (int k = threadIdx.x; k < nlev; k += BLOCK)
-        cnt[k] = 0;
+    __syncthreads();
 }
 
 __device__ int levels_at(int i)
@@ -220,29 +232,43 @@ template <bool LDS>
 __device__ __attribute__((noinline)) void run_image(const ImgDesc* __restrict__ dp, uint64_t* smem, lds_u32* cnt)
 {
     const Img<LDS> g = make_img<LDS>(dp, smem);
-    pack_image(dp->X, dp->C, dp->ld, g);
-    clear_phase(g, cnt, HASF_LEVELS_MAX);
+    pack_rows(dp->X, dp->C, dp->ld, g.H, g.W, g.R, g.hasK ? g.K : nullptr);
+    for (int k = threadIdx.x; k < HASF_LEVELS_MAX; k += BLOCK)
+        cnt[k] = 0;
+    __syncthreads();
+    rows_to_sub(g);
     __syncthreads();
     const int r = dp->r;
     for (int i = 1; i <= r; ++i) {
         const int nlev = levels_at(i);
         // HC_i (eq. i): thin, then thicken; HF_i (eq. ii): thicken, then thin
         for (int ph = 0; ph < 4; ++ph) {
+            if (i > 1 || ph > 0) {
+                sub_to_rows(g);
+                __syncthreads();
+            }
             run_stage<LDS>(dp, smem, i, ph, cnt);
             __syncthreads();
+            clear_candidates(g);
+            __syncthreads();
             level_loop<LDS>(dp, smem, ph == HC_THIN || ph == HF_THIN, nlev, cnt);
-            clear_phase(g, cnt, nlev);
+            for (int k = threadIdx.x; k < nlev; k += BLOCK)
+                cnt[k] = 0;
             __syncthreads();
         }
     }
-    unpack_image(dp->X, dp->ld, g);
+    if (r > 0) {
+        sub_to_rows(g);
+        __syncthreads();
+    }
+    unpack_rows(dp->X, dp->ld, g.H, g.W, g.R);
 }
 
 }  // namespace
 
 // Each workgroup claims images in queue order until the queue is empty.
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void hasf_filter_kernel(const ImgDesc* __restrict__ desc, int n,
-                                                            int* __restrict__ next)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void hasf_filter_kernel(
+    const ImgDesc* __restrict__ desc, int n, int* __restrict__ next)
 {
     extern __shared__ uint64_t smem[];
     __shared__ unsigned cnt[HASF_LEVELS_MAX];

@@ -49,10 +49,11 @@ __device__ unsigned block_exclusive_scan(unsigned v, unsigned* out_prefix, unsig
     return total;
 }
 
-template <bool LDS, typename PP>
-__device__ __forceinline__ bool bit_at(const Img<LDS>& g, PP plane, int i, int j)
+// bit (i, j) of a row-major plane
+template <typename PP>
+__device__ __forceinline__ bool bit_at(PP plane, int WW, int i, int j)
 {
-    return (plane[g.at(i, j >> 6)] >> (j & 63)) & 1ull;
+    return (plane[i * WW + (j >> 6)] >> (j & 63)) & 1ull;
 }
 
 template <bool LDS>
@@ -62,51 +63,30 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     Img<LDS> g;
     g.H = a.H;
     g.W = a.W;
-    g.WW = (a.W + 63) >> 6;
-    g.NWD = g.H * g.WW;
-    g.E = ((g.H + 1) >> 1) * g.WW;
-    g.lastmask = (a.W & 63) ? ((1ull << (a.W & 63)) - 1ull) : ~0ull;
-    glb_u64* gp = (glb_u64*)a.planes;
+    glb_u8* gp = (glb_u8*)a.planes;
+    size_t boff = 0;
     if constexpr (LDS) {
-        g.S = (lds_u64*)smem;
-        g.M = (lds_u64*)smem + g.NWD;
-        g.D0 = (lds_u8*)((lds_u64*)smem + 2 * (size_t)g.NWD);
+        bind_state(g, (void*)smem);
     } else {
-        g.S = gp;
-        g.M = gp + g.NWD;
-        g.D0 = (glb_u8*)(gp + 3 * (size_t)g.NWD);
+        bind_state(g, (void*)gp);
+        boff = (state_bytes(a.H, a.W) + 255) / 256 * 256;
     }
-    g.D1 = g.D0 + g.NWD;
-    glb_u64* Bp = gp + 2 * (size_t)g.NWD;
-    g.A = Bp;
-    g.K = Bp;
+    glb_u64* Bp = (glb_u64*)(gp + boff);  // row-major bits of B
+    g.A = nullptr;
+    g.K = nullptr;
     g.hasK = false;
     g.eidx = nullptr;
     g.emsk = nullptr;
     const int N = a.H * a.W;
+    const int WW = g.WW;
 
-    // X -> S; B -> Bp (pack_image writes X's bits; B is packed on its own)
-    pack_image(a.X, (const uint8_t*)nullptr, a.ld, g);
-    {
-        Img<false> gb;
-        gb.H = g.H;
-        gb.W = g.W;
-        gb.WW = g.WW;
-        gb.NWD = g.NWD;
-        gb.E = g.E;
-        gb.S = Bp;
-        gb.hasK = false;
-        if (a.B)
-            pack_image(a.B, (const uint8_t*)nullptr, a.ld, gb);
-        else
-            for (int q = threadIdx.x; q < g.NWD; q += BLOCK)
-                Bp[q] = 0;
-    }
-    for (int q = threadIdx.x; q < g.NWD; q += BLOCK) {
-        g.M[q] = 0;
-        g.D0[q] = 0;
-        g.D1[q] = 0;
-    }
+    // X -> R, B -> Bp (row-major); R is read below until the sub-images are built
+    pack_rows(a.X, (const uint8_t*)nullptr, a.ld, a.H, a.W, g.R, (glb_u64*)nullptr);
+    if (a.B)
+        pack_rows(a.B, (const uint8_t*)nullptr, a.ld, a.H, a.W, Bp, (glb_u64*)nullptr);
+    else
+        for (int q = threadIdx.x; q < g.NWD; q += BLOCK)
+            Bp[q] = 0;
     glb_u64* bm = (glb_u64*)a.bitmap;
     for (unsigned long long q = threadIdx.x; q < a.nbw; q += BLOCK)
         bm[q] = 0;
@@ -115,7 +95,7 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     // mark the priority values of the candidates
     for (int p = threadIdx.x; p < N; p += BLOCK) {
         const int i = p / a.W, j = p - i * a.W;
-        const bool s = bit_at(g, g.S, i, j), b = bit_at(g, Bp, i, j);
+        const bool s = bit_at(g.R, WW, i, j), b = bit_at(Bp, WW, i, j);
         if (a.thin ? (s && !b) : (!s && b)) {
             const uint32_t v = a.P[(size_t)i * a.W + j];
             if (v != 0xFFFFFFFFu)
@@ -146,7 +126,7 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     // count candidates per level
     for (int p = threadIdx.x; p < N; p += BLOCK) {
         const int i = p / a.W, j = p - i * a.W;
-        const bool s = bit_at(g, g.S, i, j), b = bit_at(g, Bp, i, j);
+        const bool s = bit_at(g.R, WW, i, j), b = bit_at(Bp, WW, i, j);
         if (a.thin ? (s && !b) : (!s && b)) {
             const uint32_t v = a.P[(size_t)i * a.W + j];
             if (v != 0xFFFFFFFFu) {
@@ -177,7 +157,7 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     g32* ent = (g32*)a.ent;
     for (int p = threadIdx.x; p < N; p += BLOCK) {
         const int i = p / a.W, j = p - i * a.W;
-        const bool s = bit_at(g, g.S, i, j), b = bit_at(g, Bp, i, j);
+        const bool s = bit_at(g.R, WW, i, j), b = bit_at(Bp, WW, i, j);
         if (a.thin ? (s && !b) : (!s && b)) {
             const uint32_t v = a.P[(size_t)i * a.W + j];
             if (v != 0xFFFFFFFFu) {
@@ -190,6 +170,10 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
         }
     }
     __syncthreads();
+    rows_to_sub(g);
+    __syncthreads();
+    clear_candidates(g);  // R is no longer needed
+    __syncthreads();
 
     // levels in increasing order
     for (unsigned k = 0; k < nlev; ++k) {
@@ -197,15 +181,15 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
         for (unsigned t = e0 + threadIdx.x; t < e1; t += BLOCK) {
             const unsigned p = ent[t];
             const int i = (int)(p / (unsigned)a.W), j = (int)(p - (unsigned)i * (unsigned)a.W);
-            const int q = g.at(i, j >> 6);
-            __hip_atomic_fetch_or(g.M + q, 1ull << (j & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            g.D0[q] = 1;
-            g.D1[q] = 1;
+            activate_pixel(g, i, j);
         }
         __syncthreads();
         run_rounds(g, a.thin != 0);
     }
-    unpack_image(a.X, a.ld, g);
+    __syncthreads();
+    sub_to_rows(g);
+    __syncthreads();
+    unpack_rows(a.X, a.ld, a.H, a.W, g.R);
 }
 
 }  // namespace
