@@ -305,8 +305,8 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
         const size_t WW = (size_t)(im.W + 63) / 64;
         const size_t NWD = (size_t)im.H * WW;
         // LDS: S and M planes (8 B/word each) and the two flag bytes per word
-        const size_t sb = align256(state_bytes(im.H, im.W));
-        const bool lds = sb <= lds_cap;
+        const bool lds = align256(state_bytes(im.H, im.W, true)) <= lds_cap;
+        const size_t sb = align256(state_bytes(im.H, im.W, lds));
         const size_t nlev = (size_t)std::max(1, levels_host(im.r));
         ImgDesc& d = desc[q];
         d.X = im.X;
@@ -407,8 +407,8 @@ hasf_status run_topo(hasf_ctx* ctx, uint8_t* X, const uint8_t* B, int H, int W, 
     }
     const unsigned long long nbw = vmax / 64 + 1;
     const size_t lds_cap = std::min(ctx->lds_per_block, (size_t)160 * 1024) - 4096;
-    const size_t sb = align256(state_bytes(H, W));
-    const bool lds = sb <= lds_cap;
+    const bool lds = align256(state_bytes(H, W, true)) <= lds_cap;
+    const size_t sb = align256(state_bytes(H, W, lds));
     size_t off = 0;
     const size_t oP = off; off += align256(N * 4);
     const size_t oE = off; off += align256(edt_scratch_bytes(H, W));

@@ -106,11 +106,15 @@ constexpr int HASF_LEVELS_MAX = level_count(HASF_R_MAX);
 //   M  the activated candidates, same layout; its memory also holds R, the
 //      row-major view of S (64 columns per 64-bit word) that the distance
 //      stages read, while no candidate is active;
-//   D  one byte per sub-image word: the word must be re-tested.
-__host__ __device__ inline size_t state_bytes(int H, int W)
+//   D  one byte per sub-image word: the word must be re-tested;
+//   L  the live words of the running pass.
+__host__ __device__ inline size_t state_bytes(int H, int W, bool lds)
 {
     const size_t WW = (size_t)(W + 63) / 64, HH = (size_t)(H + 1) / 2;
-    return 36 * HH * WW;
+    const size_t SUB = (HH * WW + 3) & ~(size_t)3;
+    // S and M: 4 sub-images of 4-byte words; D: 1 byte per word; the live list
+    // of a pass: 2-byte (LDS) or 4-byte (global) word indices
+    return 36 * SUB + (lds ? 2 : 4) * SUB;
 }
 
 // ---------------------------------------------------------------------------

@@ -18,6 +18,8 @@ typedef __attribute__((address_space(3))) uint32_t lds_u32;
 typedef __attribute__((address_space(1))) uint32_t glb_u32;
 typedef __attribute__((address_space(3))) uint8_t lds_u8;
 typedef __attribute__((address_space(1))) uint8_t glb_u8;
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+typedef __attribute__((address_space(3))) int lds_i32;
 
 enum StageMode {
     HC_THIN = 0,     // features = complement u outside; base = S \ K; saves S into A
@@ -55,10 +57,14 @@ struct Img {
     using P64 = typename std::conditional<LDS, lds_u64*, glb_u64*>::type;
     using P32 = typename std::conditional<LDS, lds_u32*, glb_u32*>::type;
     using P8 = typename std::conditional<LDS, lds_u8*, glb_u8*>::type;
+    // list of the live words of a pass (16-bit indices in LDS, 32-bit in global)
+    using PL = typename std::conditional<LDS, lds_u16*, glb_u32*>::type;
     P64 R;        // row-major view of the current set (distance stages)
     P32 S;        // current set, four sub-images
     P32 M;        // activated candidates, four sub-images (shares memory with R)
     P8 D;         // per sub-image word: must be re-tested
+    PL L;         // live words of the running pass
+    lds_i32* ctl; // control words in LDS, see run_rounds
     glb_u64* A;   // set saved before the phase (row-major)
     glb_u64* K;   // constraint set (row-major)
     glb_u32* eidx;
@@ -77,12 +83,13 @@ __device__ __forceinline__ void bind_state(Img<LDS>& g, void* base)
     g.WW = (g.W + 63) >> 6;
     g.NWD = g.H * g.WW;
     g.HH = (g.H + 1) >> 1;
-    g.SUB = g.HH * g.WW;
+    g.SUB = (g.HH * g.WW + 3) & ~3;
     g.lastmask = (g.W & 63) ? ((1ull << (g.W & 63)) - 1ull) : ~0ull;
     g.S = (typename Img<LDS>::P32)base;
     g.M = g.S + 4 * (size_t)g.SUB;
     g.R = (typename Img<LDS>::P64)g.M;
     g.D = (typename Img<LDS>::P8)(g.M + 4 * (size_t)g.SUB);
+    g.L = (typename Img<LDS>::PL)(g.D + 4 * (size_t)g.SUB);
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt()
@@ -218,9 +225,40 @@ __device__ void clear_candidates(const Img<LDS>& g)
     }
 }
 
+// Control words (LDS). Every activation and every executed pass gets a
+// serial number, uniform across the workgroup and strictly increasing within
+// a phase. chg holds the serial of the last pass that changed a pixel;
+// prod[s] the serial of the last activation or pass that flagged a word of
+// sub-image s; cnt[2] are the live-list lengths of alternate passes. A pass
+// of sub-image s runs only if prod[s] grew since it last ran; a round changed
+// the set iff chg exceeds the serial at the start of the round. These words
+// are only written between the barriers that separate them from their
+// readers (prod[s] never by the pass of s), so every thread takes the same
+// decisions without extra synchronisation.
+enum { CTL_CHG = 0, CTL_CNT = 2, CTL_PROD = 4, CTL_WORDS = 8 };
+
+// per-phase scheduling state (uniform registers)
+struct Sched {
+    int serial;       // last serial handed out
+    int npass;        // executed passes (selects the live-list length word)
+    int consumed[4];  // prod value seen when the sub-image's pass last ran
+};
+
+// start of a phase; needs a barrier before the first activation
+template <bool LDS>
+__device__ __forceinline__ void sched_reset(const Img<LDS>& g, Sched& sc)
+{
+    sc.serial = 0;
+    sc.npass = 0;
+    for (int k = 0; k < 4; ++k)
+        sc.consumed[k] = 0;
+    if (threadIdx.x < CTL_WORDS)
+        g.ctl[threadIdx.x] = 0;
+}
+
 // activate the candidate bits `m` of row-major word (row, w)
 template <bool LDS>
-__device__ __forceinline__ void activate_row_word(const Img<LDS>& g, int row, int w, uint64_t m)
+__device__ __forceinline__ void activate_row_word(const Img<LDS>& g, int row, int w, uint64_t m, int serial)
 {
     const int o = (row >> 1) * g.WW + w;
     const uint32_t e = even_bits(m), od = even_bits(m >> 1);
@@ -228,22 +266,35 @@ __device__ __forceinline__ void activate_row_word(const Img<LDS>& g, int row, in
         const int q = g.sub(row & 1, 0) + o;
         __hip_atomic_fetch_or(g.M + q, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         g.D[q] = 1;
+        g.ctl[CTL_PROD + (row & 1) * 2] = serial;
     }
     if (od) {
         const int q = g.sub(row & 1, 1) + o;
         __hip_atomic_fetch_or(g.M + q, od, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         g.D[q] = 1;
+        g.ctl[CTL_PROD + (row & 1) * 2 + 1] = serial;
     }
 }
 
 // activate pixel (i, j)
 template <bool LDS>
-__device__ __forceinline__ void activate_pixel(const Img<LDS>& g, int i, int j)
+__device__ __forceinline__ void activate_pixel(const Img<LDS>& g, int i, int j, int serial)
 {
     const int c = j >> 1;
     const int q = g.sub(i & 1, j & 1) + (i >> 1) * g.WW + (c >> 5);
     __hip_atomic_fetch_or(g.M + q, 1u << (c & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     g.D[q] = 1;
+    g.ctl[CTL_PROD + (i & 1) * 2 + (j & 1)] = serial;
+}
+
+// exclusive prefix over the wave of v in [0, 7]; *total = sum over the wave.
+// Bit-sliced with ballots: no cross-lane data movement through LDS.
+__device__ __forceinline__ unsigned wave_prefix(unsigned v, unsigned* total)
+{
+    const uint64_t lt = lanemask_lt();
+    const uint64_t b0 = __ballot(v & 1u), b1 = __ballot(v & 2u), b2 = __ballot(v & 4u);
+    *total = (unsigned)(__popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2));
+    return (unsigned)(__popcll(b0 & lt) + 2 * __popcll(b1 & lt) + 4 * __popcll(b2 & lt));
 }
 
 // Rounds of the four subfield passes (even,even) (even,odd) (odd,even)
@@ -260,31 +311,27 @@ __device__ __forceinline__ void activate_pixel(const Img<LDS>& g, int i, int j)
 // a word it reads. An unflagged word would test exactly as before (no simple
 // candidate), so skipping it leaves the schedule and its result unchanged.
 // A pass only clears the flags of its own sub-image and only sets flags of
-// the other three, so flags need no atomics.
+// the other three, so flags need no atomics. A pass first collects its
+// flagged live words into a list (4 flags per thread per load), then tests
+// the list densely; a pass whose sub-image has no flagged word is skipped.
 template <bool LDS>
-__device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin)
+__device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& sc)
 {
     const int WW = g.WW;
-    const int rstep = BLOCK / WW;  // rows covered per sweep step
-    const int my_r = threadIdx.x / WW;
-    const int my_w = threadIdx.x - my_r * WW;
-    const bool active = my_r < rstep;
+    const float invWW = 1.0f / (float)WW;
     const uint32_t flip = thin ? 0u : ~0u;  // live = M & (S ^ flip)
-    const bool hasL = my_w > 0, hasR = my_w + 1 < WW;
-    // "something changed in round n" lives in chg[n & 1]: written by any
-    // changer, read by all after the round's last barrier, and cleared for
-    // round n + 1 after the first barrier of round n (when every thread has
-    // read the flag of round n - 1)
-    __shared__ int chg[2];
-    if (threadIdx.x == 0) {
-        chg[0] = 0;
-        chg[1] = 0;
-    }
-    __syncthreads();
-    for (int round = 0;; ++round) {
-        int changed = 0;
+    lds_i32* chg = g.ctl + CTL_CHG;
+    lds_i32* lcnt = g.ctl + CTL_CNT;
+    lds_i32* prod = g.ctl + CTL_PROD;
+    for (;;) {
+        const int round_start = sc.serial;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
+            const int p = prod[s];
+            if (p <= sc.consumed[s])
+                continue;  // nothing flagged in this sub-image: the pass would change nothing
+            sc.consumed[s] = p;
+            const int ser = ++sc.serial;
             const int si = s >> 1, sj = s & 1;
             const int so = 1 - si, co = 1 - sj;
             const auto Ss = g.S + g.sub(si, sj);
@@ -297,85 +344,143 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin)
             const auto Dy = g.D + g.sub(so, sj);
             const auto Dxy = g.D + g.sub(so, co);
             const int rows = (g.H - si + 1) >> 1;
-            if (active) {
-                for (int rr = my_r; rr < rows; rr += rstep) {
-                    const int idx = rr * WW + my_w;
-                    if (!Ds[idx])
-                        continue;
-                    Ds[idx] = 0;
-                    const uint32_t sc = Ss[idx];
-                    const uint32_t live = Ms[idx] & (sc ^ flip);
-                    if (!live)
-                        continue;
-                    const int row = 2 * rr + si;
-                    const bool hasN = row > 0, hasS = row + 1 < g.H;
-                    const int iN = (si ? rr : rr - 1) * WW + my_w;  // row - 1 in the other parity
-                    const int iS = (si ? rr + 1 : rr) * WW + my_w;  // row + 1
-                    const uint32_t xc = Sx[idx];
-                    const uint32_t xl = hasL ? Sx[idx - 1] : 0u;
-                    const uint32_t xr = hasR ? Sx[idx + 1] : 0u;
-                    const uint32_t n = hasN ? Sy[iN] : 0u;
-                    const uint32_t sv = hasS ? Sy[iS] : 0u;
-                    const uint32_t nc = hasN ? Sxy[iN] : 0u;
-                    const uint32_t nl = hasN && hasL ? Sxy[iN - 1] : 0u;
-                    const uint32_t nr = hasN && hasR ? Sxy[iN + 1] : 0u;
-                    const uint32_t dc = hasS ? Sxy[iS] : 0u;
-                    const uint32_t dl = hasS && hasL ? Sxy[iS - 1] : 0u;
-                    const uint32_t dr = hasS && hasR ? Sxy[iS + 1] : 0u;
-                    // column c of this sub-image is image column 2c + sj; its
-                    // east neighbour is column c (sj = 0) or c + 1 (sj = 1) of
-                    // the other column parity, its west one c - 1 or c
-                    uint32_t e, w, ne, nw, se, sw;
-                    if (sj == 0) {
-                        e = xc;
-                        w = (xc << 1) | (xl >> 31);
-                        ne = nc;
-                        nw = (nc << 1) | (nl >> 31);
-                        se = dc;
-                        sw = (dc << 1) | (dl >> 31);
-                    } else {
-                        e = (xc >> 1) | (xr << 31);
-                        w = xc;
-                        ne = (nc >> 1) | (nr << 31);
-                        nw = nc;
-                        se = (dc >> 1) | (dr << 31);
-                        sw = dc;
-                    }
-                    const uint32_t del = live & simple_bits<uint32_t>(e, ne, n, nw, w, sw, sv, se);
-                    if (del) {
-                        Ss[idx] = sc ^ del;  // thin clears, thicken sets the bits of del
-                        changed = 1;
-                        Dx[idx] = 1;
-                        if (hasL)
-                            Dx[idx - 1] = 1;
-                        if (hasR)
-                            Dx[idx + 1] = 1;
-                        if (hasN) {
-                            Dy[iN] = 1;
-                            Dxy[iN] = 1;
-                            if (hasL)
-                                Dxy[iN - 1] = 1;
-                            if (hasR)
-                                Dxy[iN + 1] = 1;
-                        }
-                        if (hasS) {
-                            Dy[iS] = 1;
-                            Dxy[iS] = 1;
-                            if (hasL)
-                                Dxy[iS - 1] = 1;
-                            if (hasR)
-                                Dxy[iS + 1] = 1;
+            const int nw = rows * WW;
+            lds_i32* cnt = lcnt + (sc.npass & 1);
+            // collect: flagged words whose activated candidates are still live;
+            // every lane runs the same number of iterations (wave-wide prefix)
+            const int niter = (nw + 4 * BLOCK - 1) / (4 * BLOCK);
+            for (int it = 0; it < niter; ++it) {
+                const int b0 = 4 * threadIdx.x + it * 4 * BLOCK;
+                unsigned f4 = 0;
+                if (b0 < nw)
+                    f4 = *(const typename std::conditional<LDS, lds_u32*, glb_u32*>::type)(Ds + b0);
+                unsigned nl = 0;
+                int q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+                if (f4) {
+                    *(typename std::conditional<LDS, lds_u32*, glb_u32*>::type)(Ds + b0) = 0u;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int q = b0 + j;
+                        if (((f4 >> (8 * j)) & 0xFFu) && q < nw && (Ms[q] & (Ss[q] ^ flip))) {
+                            if (nl == 0) q0 = q;
+                            else if (nl == 1) q1 = q;
+                            else if (nl == 2) q2 = q;
+                            else q3 = q;
+                            ++nl;
                         }
                     }
                 }
+                unsigned tot;
+                const unsigned off = wave_prefix(nl, &tot);
+                unsigned base = 0;
+                if (tot) {
+                    if ((threadIdx.x & 63) == 0)
+                        base = (unsigned)__hip_atomic_fetch_add(cnt, (int)tot, __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_WORKGROUP);
+                    base = (unsigned)__builtin_amdgcn_readfirstlane((int)base) + off;
+                    if (nl > 0) g.L[base] = q0;
+                    if (nl > 1) g.L[base + 1] = q1;
+                    if (nl > 2) g.L[base + 2] = q2;
+                    if (nl > 3) g.L[base + 3] = q3;
+                }
             }
-            if (changed)
-                chg[round & 1] = 1;
             __syncthreads();
-            if (s == 0 && threadIdx.x == 0)
-                chg[(round + 1) & 1] = 0;
+            if (threadIdx.x == 0)
+                lcnt[(sc.npass + 1) & 1] = 0;  // every thread read it one pass ago
+            const int n = *cnt;
+            // test the listed words
+            bool changed_here = false;
+            for (int t = threadIdx.x; t < n; t += BLOCK) {
+                const int idx = (int)g.L[t];
+                int rr = (int)((float)idx * invWW);
+                if (rr * WW > idx)
+                    --rr;
+                else if ((rr + 1) * WW <= idx)
+                    ++rr;
+                const int my_w = idx - rr * WW;
+                const bool hasL = my_w > 0, hasR = my_w + 1 < WW;
+                const uint32_t scw = Ss[idx];
+                const uint32_t live = Ms[idx] & (scw ^ flip);
+                const int row = 2 * rr + si;
+                const bool hasN = row > 0, hasS = row + 1 < g.H;
+                const int iN = (si ? rr : rr - 1) * WW + my_w;  // row - 1 in the other parity
+                const int iS = (si ? rr + 1 : rr) * WW + my_w;  // row + 1
+                const uint32_t xc = Sx[idx];
+                const uint32_t xl = hasL ? Sx[idx - 1] : 0u;
+                const uint32_t xr = hasR ? Sx[idx + 1] : 0u;
+                const uint32_t nn = hasN ? Sy[iN] : 0u;
+                const uint32_t sv = hasS ? Sy[iS] : 0u;
+                const uint32_t nc = hasN ? Sxy[iN] : 0u;
+                const uint32_t nl = hasN && hasL ? Sxy[iN - 1] : 0u;
+                const uint32_t nr = hasN && hasR ? Sxy[iN + 1] : 0u;
+                const uint32_t dc = hasS ? Sxy[iS] : 0u;
+                const uint32_t dl = hasS && hasL ? Sxy[iS - 1] : 0u;
+                const uint32_t dr = hasS && hasR ? Sxy[iS + 1] : 0u;
+                // column c of this sub-image is image column 2c + sj; its east
+                // neighbour is column c (sj = 0) or c + 1 (sj = 1) of the other
+                // column parity, its west one c - 1 or c
+                uint32_t e, w, ne, nw2, se, sw;
+                if (sj == 0) {
+                    e = xc;
+                    w = (xc << 1) | (xl >> 31);
+                    ne = nc;
+                    nw2 = (nc << 1) | (nl >> 31);
+                    se = dc;
+                    sw = (dc << 1) | (dl >> 31);
+                } else {
+                    e = (xc >> 1) | (xr << 31);
+                    w = xc;
+                    ne = (nc >> 1) | (nr << 31);
+                    nw2 = nc;
+                    se = (dc >> 1) | (dr << 31);
+                    sw = dc;
+                }
+                const uint32_t del = live & simple_bits<uint32_t>(e, ne, nn, nw2, w, sw, sv, se);
+                if (del) {
+                    changed_here = true;
+                    Ss[idx] = scw ^ del;  // thin clears, thicken sets the bits of del
+                    Dx[idx] = 1;
+                    if (hasL)
+                        Dx[idx - 1] = 1;
+                    if (hasR)
+                        Dx[idx + 1] = 1;
+                    if (hasN) {
+                        Dy[iN] = 1;
+                        Dxy[iN] = 1;
+                        if (hasL)
+                            Dxy[iN - 1] = 1;
+                        if (hasR)
+                            Dxy[iN + 1] = 1;
+                    }
+                    if (hasS) {
+                        Dy[iS] = 1;
+                        Dxy[iS] = 1;
+                        if (hasL)
+                            Dxy[iS - 1] = 1;
+                        if (hasR)
+                            Dxy[iS + 1] = 1;
+                    }
+                }
+            }
+            // one lane per wave records the change (a same-address store from
+            // many lanes would be serialised)
+            {
+                const uint64_t chm = __ballot(changed_here);
+                if (chm && (int)(threadIdx.x & 63) == __ffsll((long long)chm) - 1) {
+                    *chg = ser;
+                    prod[si * 2 + co] = ser;
+                    if (g.H > 1) {
+                        prod[so * 2 + sj] = ser;
+                        prod[so * 2 + co] = ser;
+                    }
+                }
+            }
+            __syncthreads();
+            ++sc.npass;
         }
-        if (!chg[round & 1])
+        // a round changed nothing (and the level is done) iff no pass of it
+        // stored its serial in chg; a round without any pass changes nothing
+        if (*chg <= round_start)
             break;
     }
 }

@@ -39,9 +39,10 @@ __device__ __forceinline__ uint64_t feat_word(const Img<LDS>& g, int row, int w,
 }
 
 template <bool LDS>
-__device__ __forceinline__ Img<LDS> make_img(const ImgDesc* __restrict__ dp, uint64_t* smem)
+__device__ __forceinline__ Img<LDS> make_img(const ImgDesc* __restrict__ dp, uint64_t* smem, lds_i32* ctl)
 {
     Img<LDS> g;
+    g.ctl = ctl;
     g.H = dp->H;
     g.W = dp->W;
     glb_u64* gp = (glb_u64*)dp->gplanes;
@@ -52,7 +53,7 @@ __device__ __forceinline__ Img<LDS> make_img(const ImgDesc* __restrict__ dp, uin
         g.K = gp + NWD;
     } else {
         bind_state(g, (void*)gp);
-        const size_t sb = (state_bytes(g.H, g.W) + 255) / 256 * 256;
+        const size_t sb = (state_bytes(g.H, g.W, false) + 255) / 256 * 256;
         g.A = (glb_u64*)((glb_u8*)gp + sb);
         g.K = g.A + NWD;
     }
@@ -91,9 +92,9 @@ __device__ __forceinline__ void flush_level(const Img<LDS>& g, lds_u32* cnt, int
 // level entry lists.
 template <int I, bool LDS>
 __device__ __attribute__((noinline)) void stage(const ImgDesc* __restrict__ dp, uint64_t* smem, int mode,
-                                                lds_u32* cnt)
+                                                lds_u32* cnt, lds_i32* ctl)
 {
-    const Img<LDS> g = make_img<LDS>(dp, smem);
+    const Img<LDS> g = make_img<LDS>(dp, smem, ctl);
     constexpr BallPairs P = make_ball_pairs(I);
     const bool frame = (mode == HC_THIN || mode == HF_THIN);
     // all lanes of a wave iterate the same number of times so that the
@@ -173,24 +174,25 @@ __device__ __attribute__((noinline)) void stage(const ImgDesc* __restrict__ dp, 
 }
 
 template <bool LDS>
-__device__ __forceinline__ void run_stage(const ImgDesc* dp, uint64_t* smem, int i, int mode, lds_u32* cnt)
+__device__ __forceinline__ void run_stage(const ImgDesc* dp, uint64_t* smem, int i, int mode, lds_u32* cnt,
+                                          lds_i32* ctl)
 {
     switch (i) {
-    case 1: stage<1, LDS>(dp, smem, mode, cnt); break;
-    case 2: stage<2, LDS>(dp, smem, mode, cnt); break;
-    case 3: stage<3, LDS>(dp, smem, mode, cnt); break;
-    case 4: stage<4, LDS>(dp, smem, mode, cnt); break;
-    case 5: stage<5, LDS>(dp, smem, mode, cnt); break;
-    case 6: stage<6, LDS>(dp, smem, mode, cnt); break;
-    case 7: stage<7, LDS>(dp, smem, mode, cnt); break;
-    case 8: stage<8, LDS>(dp, smem, mode, cnt); break;
-    case 9: stage<9, LDS>(dp, smem, mode, cnt); break;
-    case 10: stage<10, LDS>(dp, smem, mode, cnt); break;
-    case 11: stage<11, LDS>(dp, smem, mode, cnt); break;
-    case 12: stage<12, LDS>(dp, smem, mode, cnt); break;
-    case 13: stage<13, LDS>(dp, smem, mode, cnt); break;
-    case 14: stage<14, LDS>(dp, smem, mode, cnt); break;
-    default: stage<15, LDS>(dp, smem, mode, cnt); break;
+    case 1: stage<1, LDS>(dp, smem, mode, cnt, ctl); break;
+    case 2: stage<2, LDS>(dp, smem, mode, cnt, ctl); break;
+    case 3: stage<3, LDS>(dp, smem, mode, cnt, ctl); break;
+    case 4: stage<4, LDS>(dp, smem, mode, cnt, ctl); break;
+    case 5: stage<5, LDS>(dp, smem, mode, cnt, ctl); break;
+    case 6: stage<6, LDS>(dp, smem, mode, cnt, ctl); break;
+    case 7: stage<7, LDS>(dp, smem, mode, cnt, ctl); break;
+    case 8: stage<8, LDS>(dp, smem, mode, cnt, ctl); break;
+    case 9: stage<9, LDS>(dp, smem, mode, cnt, ctl); break;
+    case 10: stage<10, LDS>(dp, smem, mode, cnt, ctl); break;
+    case 11: stage<11, LDS>(dp, smem, mode, cnt, ctl); break;
+    case 12: stage<12, LDS>(dp, smem, mode, cnt, ctl); break;
+    case 13: stage<13, LDS>(dp, smem, mode, cnt, ctl); break;
+    case 14: stage<14, LDS>(dp, smem, mode, cnt, ctl); break;
+    default: stage<15, LDS>(dp, smem, mode, cnt, ctl); break;
     }
 }
 
@@ -199,20 +201,24 @@ __device__ __forceinline__ void run_stage(const ImgDesc* dp, uint64_t* smem, int
 // thickening *H, Sec. 2).
 template <bool LDS>
 __device__ __attribute__((noinline)) void level_loop(const ImgDesc* __restrict__ dp, uint64_t* smem, bool thin,
-                                                     int nlev, lds_u32* cnt)
+                                                     int nlev, lds_u32* cnt, lds_i32* ctl)
 {
-    const Img<LDS> g = make_img<LDS>(dp, smem);
+    const Img<LDS> g = make_img<LDS>(dp, smem, ctl);
+    Sched sc;
+    sched_reset(g, sc);
+    __syncthreads();
     for (int k = 0; k < nlev; ++k) {
         const unsigned c = cnt[k];
         if (c == 0)
             continue;
+        const int ser = ++sc.serial;
         const size_t e0 = (size_t)k * g.NWD;
         for (unsigned t = threadIdx.x; t < c; t += BLOCK) {
             const uint32_t p = g.eidx[e0 + t];
-            activate_row_word(g, (int)(p >> 10), (int)(p & 1023u), (uint64_t)g.emsk[e0 + t]);
+            activate_row_word(g, (int)(p >> 10), (int)(p & 1023u), (uint64_t)g.emsk[e0 + t], ser);
         }
         __syncthreads();
-        run_rounds(g, thin);
+        run_rounds(g, thin, sc);
     }
     __syncthreads();
 }
@@ -229,9 +235,10 @@ __device__ int levels_at(int i)
 }
 
 template <bool LDS>
-__device__ __attribute__((noinline)) void run_image(const ImgDesc* __restrict__ dp, uint64_t* smem, lds_u32* cnt)
+__device__ __attribute__((noinline)) void run_image(const ImgDesc* __restrict__ dp, uint64_t* smem, lds_u32* cnt,
+                                                    lds_i32* ctl)
 {
-    const Img<LDS> g = make_img<LDS>(dp, smem);
+    const Img<LDS> g = make_img<LDS>(dp, smem, ctl);
     pack_rows(dp->X, dp->C, dp->ld, g.H, g.W, g.R, g.hasK ? g.K : nullptr);
     for (int k = threadIdx.x; k < HASF_LEVELS_MAX; k += BLOCK)
         cnt[k] = 0;
@@ -247,11 +254,11 @@ __device__ __attribute__((noinline)) void run_image(const ImgDesc* __restrict__ 
                 sub_to_rows(g);
                 __syncthreads();
             }
-            run_stage<LDS>(dp, smem, i, ph, cnt);
+            run_stage<LDS>(dp, smem, i, ph, cnt, ctl);
             __syncthreads();
             clear_candidates(g);
             __syncthreads();
-            level_loop<LDS>(dp, smem, ph == HC_THIN || ph == HF_THIN, nlev, cnt);
+            level_loop<LDS>(dp, smem, ph == HC_THIN || ph == HF_THIN, nlev, cnt, ctl);
             for (int k = threadIdx.x; k < nlev; k += BLOCK)
                 cnt[k] = 0;
             __syncthreads();
@@ -272,6 +279,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 {
     extern __shared__ uint64_t smem[];
     __shared__ unsigned cnt[HASF_LEVELS_MAX];
+    __shared__ int ctl[CTL_WORDS];
     __shared__ int s_img;
     for (;;) {
         if (threadIdx.x == 0)
@@ -282,9 +290,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         if (img >= n)
             break;
         if (desc[img].lds)
-            run_image<true>(desc + img, smem, (lds_u32*)cnt);
+            run_image<true>(desc + img, smem, (lds_u32*)cnt, (lds_i32*)ctl);
         else
-            run_image<false>(desc + img, smem, (lds_u32*)cnt);
+            run_image<false>(desc + img, smem, (lds_u32*)cnt, (lds_i32*)ctl);
         __syncthreads();
     }
 }

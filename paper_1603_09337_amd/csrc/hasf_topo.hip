@@ -60,7 +60,9 @@ template <bool LDS>
 __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
 {
     __shared__ unsigned tmp[BLOCK / 64 + 1];
+    __shared__ int ctl[CTL_WORDS];
     Img<LDS> g;
+    g.ctl = (lds_i32*)ctl;
     g.H = a.H;
     g.W = a.W;
     glb_u8* gp = (glb_u8*)a.planes;
@@ -69,7 +71,7 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
         bind_state(g, (void*)smem);
     } else {
         bind_state(g, (void*)gp);
-        boff = (state_bytes(a.H, a.W) + 255) / 256 * 256;
+        boff = (state_bytes(a.H, a.W, false) + 255) / 256 * 256;
     }
     glb_u64* Bp = (glb_u64*)(gp + boff);  // row-major bits of B
     g.A = nullptr;
@@ -173,18 +175,21 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     rows_to_sub(g);
     __syncthreads();
     clear_candidates(g);  // R is no longer needed
+    Sched sc;
+    sched_reset(g, sc);
     __syncthreads();
 
     // levels in increasing order
     for (unsigned k = 0; k < nlev; ++k) {
         const unsigned e0 = k ? hist[k - 1] : 0u, e1 = hist[k];
+        const int ser = ++sc.serial;
         for (unsigned t = e0 + threadIdx.x; t < e1; t += BLOCK) {
             const unsigned p = ent[t];
             const int i = (int)(p / (unsigned)a.W), j = (int)(p - (unsigned)i * (unsigned)a.W);
-            activate_pixel(g, i, j);
+            activate_pixel(g, i, j, ser);
         }
         __syncthreads();
-        run_rounds(g, a.thin != 0);
+        run_rounds(g, a.thin != 0, sc);
     }
     __syncthreads();
     sub_to_rows(g);
