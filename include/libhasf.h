@@ -151,6 +151,62 @@ typedef struct {
  */
 hasf_status hasf_filter_batch(hasf_ctx* ctx, const hasf_image* imgs, int n);
 
+/*
+ * Served stream (continuous batching). hasf_serve starts a server on ctx's
+ * device: a persistent kernel whose idle workgroups take frames as soon as
+ * they are published, and a host dispatcher thread that admits submitted
+ * frames in arrival order when their scratch memory fits in the server's
+ * device pool (admission by HBM footprint), publishes them to the kernel and
+ * retires them as they complete. Frames that arrive while others are being
+ * filtered start on the next free workgroup, so their work overlaps on the
+ * device; each frame's result equals hasf_filter on that frame alone.
+ *
+ * Frames are device-resident: img->X (and img->C) are DEVICE pointers, filtered
+ * in place; the caller keeps them alive and untouched until the frame's
+ * hasf_serve_wait has returned. While a server runs, do not synchronise the
+ * whole device (hipDeviceSynchronize): its kernel only returns when the server
+ * stops or has been idle for opts->idle_exit_ms.
+ */
+typedef struct {
+    size_t pool_bytes;     /* device memory for frame scratch; 0 = the context's hbm_budget */
+    int ring_slots;        /* frames published at once (0 = 4096) */
+    int max_pending;       /* submitted but not admitted; beyond it submit returns HASF_EAGAIN (0 = 1 << 20) */
+    int idle_exit_ms;      /* the kernel exits after this long without work and is relaunched on demand (0 = 2000) */
+    unsigned flags;        /* reserved, must be 0 */
+} hasf_serve_opts;
+
+typedef struct hasf_server hasf_server;
+
+typedef struct {
+    int status;            /* HASF_OK, or the frame's error */
+    uint64_t ticket;
+    double submit_s;       /* host steady clock, seconds */
+    double done_s;         /* when the dispatcher saw the frame complete */
+    double latency_ms;     /* done_s - submit_s */
+} hasf_result;
+
+typedef struct {
+    uint64_t submitted, completed, rejected;
+    uint64_t pending, in_flight;
+    double p50_ms, p99_ms, max_ms;   /* latency over completed frames */
+    double frames_per_s;             /* completed / (last done - first submit) */
+    double mpixel_per_s;
+    size_t pool_bytes, pool_peak_bytes;
+    uint64_t kernel_launches;
+} hasf_stats;
+
+hasf_status hasf_serve(hasf_ctx* ctx, const hasf_serve_opts* opts, hasf_server** out);
+/* Thread-safe. Validates the frame (HASF_EINVAL, nothing queued), then queues
+ * it; HASF_EAGAIN when max_pending frames are already waiting. */
+hasf_status hasf_serve_submit(hasf_server* s, const hasf_image* img, uint64_t* ticket);
+/* Wait until the frame completes (timeout_ms < 0: forever); HASF_ETIMEDOUT if
+ * it has not completed in time (the frame stays queued). A ticket can be
+ * waited for once; out may be NULL. */
+hasf_status hasf_serve_wait(hasf_server* s, uint64_t ticket, int timeout_ms, hasf_result* out);
+hasf_status hasf_serve_stats(hasf_server* s, hasf_stats* out);
+/* Finish every submitted frame, stop the kernel and free the server. */
+hasf_status hasf_serve_stop(hasf_server* s);
+
 #ifdef __cplusplus
 }
 #endif

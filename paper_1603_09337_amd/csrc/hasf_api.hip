@@ -302,12 +302,7 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
     size_t bytes = 0, lds_need = 0;
     for (int q = 0; q < n; ++q) {
         const hasf_image& im = imgs[order[q]];
-        const size_t WW = (size_t)(im.W + 63) / 64;
-        const size_t NWD = (size_t)im.H * WW;
-        // LDS: S and M planes (8 B/word each) and the two flag bytes per word
-        const bool lds = align256(state_bytes(im.H, im.W, true)) <= lds_cap;
-        const size_t sb = align256(state_bytes(im.H, im.W, lds));
-        const size_t nlev = (size_t)std::max(1, levels_host(im.r));
+        const ImageLayout L = image_layout(im.H, im.W, im.r, lds_cap);
         ImgDesc& d = desc[q];
         d.X = im.X;
         d.C = im.C;
@@ -315,17 +310,15 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
         d.H = im.H;
         d.W = im.W;
         d.r = im.r;
-        d.lds = lds ? 1 : 0;
-        if (lds)
-            lds_need = std::max(lds_need, sb);
+        d.lds = L.lds ? 1 : 0;
+        lds_need = std::max(lds_need, L.lds_bytes);
         // offsets for now; rebased after allocation
         d.gplanes = (uint64_t*)bytes;
-        // global: [state (unless in LDS) | A | K]
-        bytes += align256((lds ? 0 : sb) + 2 * NWD * 8);
+        bytes += L.planes_bytes;
         d.ent_idx = (uint32_t*)bytes;
-        bytes += align256(nlev * NWD * 4);
+        bytes += L.idx_bytes;
         d.ent_msk = (uint64_t*)bytes;
-        bytes += align256(nlev * NWD * 8);
+        bytes += L.msk_bytes;
     }
     const size_t desc_bytes = align256(256 + sizeof(ImgDesc) * (size_t)n);
     hasf_status s = ensure_scratch(ctx, bytes + desc_bytes);

@@ -131,6 +131,38 @@ struct ImgDesc {
     uint64_t* ent_msk;  // level entries: candidate bits
 };
 
+// Scratch of one image in the filter kernel: global bytes for the state (when
+// it does not fit in LDS), the saved set A and the constraint K, and the level
+// entry lists (one slot per word per level).
+struct ImageLayout {
+    bool lds;
+    size_t lds_bytes;     // dynamic LDS the image needs (0 if it is in global memory)
+    size_t planes_bytes;  // [state (unless LDS) | A | K]
+    size_t idx_bytes, msk_bytes;
+    size_t total() const { return planes_bytes + idx_bytes + msk_bytes; }
+};
+
+inline size_t hasf_align256(size_t x) { return (x + 255) / 256 * 256; }
+
+inline int hasf_levels(int r)
+{
+    return level_count(r);
+}
+
+inline ImageLayout image_layout(int H, int W, int r, size_t lds_cap)
+{
+    ImageLayout L;
+    const size_t WW = (size_t)(W + 63) / 64, NWD = (size_t)H * WW;
+    L.lds = hasf_align256(state_bytes(H, W, true)) <= lds_cap;
+    const size_t sb = hasf_align256(state_bytes(H, W, L.lds));
+    L.lds_bytes = L.lds ? sb : 0;
+    L.planes_bytes = hasf_align256((L.lds ? 0 : sb) + 2 * NWD * 8);
+    const size_t nlev = (size_t)(r > 0 ? hasf_levels(r) : 1);
+    L.idx_bytes = hasf_align256(nlev * NWD * 4);
+    L.msk_bytes = hasf_align256(nlev * NWD * 8);
+    return L;
+}
+
 // Arguments of the standalone thinning / thickening kernel.
 namespace hasf_detail {
 

@@ -37,7 +37,32 @@ class _Image(ctypes.Structure):
                 ("ld", ctypes.c_int64), ("r", ctypes.c_int)]
 
 
+class _ServeOpts(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_size_t), ("ring_slots", ctypes.c_int), ("max_pending", ctypes.c_int),
+                ("idle_exit_ms", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("ticket", ctypes.c_uint64), ("submit_s", ctypes.c_double),
+                ("done_s", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("pending", ctypes.c_uint64), ("in_flight", ctypes.c_uint64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("frames_per_s", ctypes.c_double),
+                ("mpixel_per_s", ctypes.c_double), ("pool_bytes", ctypes.c_size_t),
+                ("pool_peak_bytes", ctypes.c_size_t), ("kernel_launches", ctypes.c_uint64)]
+
+
 _vp = ctypes.c_void_p
+_lib.hasf_serve.argtypes = [_vp, ctypes.POINTER(_ServeOpts), ctypes.POINTER(_vp)]
+_lib.hasf_serve_submit.argtypes = [_vp, ctypes.POINTER(_Image), ctypes.POINTER(ctypes.c_uint64)]
+_lib.hasf_serve_wait.argtypes = [_vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(_Result)]
+_lib.hasf_serve_stats.argtypes = [_vp, ctypes.POINTER(_Stats)]
+_lib.hasf_serve_stop.argtypes = [_vp]
+for _f in ("hasf_serve", "hasf_serve_submit", "hasf_serve_wait", "hasf_serve_stats", "hasf_serve_stop"):
+    getattr(_lib, _f).restype = ctypes.c_int
 _lib.hasf_create.argtypes = [ctypes.POINTER(_Opts), ctypes.POINTER(_vp)]
 _lib.hasf_destroy.argtypes = [_vp]
 _lib.hasf_destroy.restype = None
@@ -67,12 +92,6 @@ class HasfError(RuntimeError):
 
 def lib():
     return _lib
-
-
-def exported_symbols():
-    return [n for n in ("hasf_create", "hasf_destroy", "hasf_set_stream", "hasf_sync", "hasf_strerror",
-                        "hasf_last_error", "hasf_simple_lut", "hasf_edt_sq", "hasf_homotopic_thin",
-                        "hasf_homotopic_thicken", "hasf_filter", "hasf_filter_batch")]
 
 
 def simple_lut(n: int = 8):
@@ -187,3 +206,73 @@ class Context:
         self._stream()
         self._check(_lib.hasf_filter_batch(self._h, arr, len(items)))
         return [X for X, _, _ in items]
+
+
+class Server:
+    """Served stream on a context's device (hasf_serve). Frames are device
+    tensors filtered in place; keep them alive until wait() returns."""
+
+    def __init__(self, ctx: Context, pool_bytes: int = 0, ring_slots: int = 0, max_pending: int = 0,
+                 idle_exit_ms: int = 0):
+        self._ctx = ctx
+        h = _vp()
+        opts = _ServeOpts(pool_bytes, ring_slots, max_pending, idle_exit_ms, 0)
+        st = _lib.hasf_serve(ctx._h, ctypes.byref(opts), ctypes.byref(h))
+        if st != HASF_OK:
+            raise HasfError(st, "hasf_serve")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, X, C=None, r: int = 1, check: bool = True):
+        """Queue a frame; returns its ticket (or the status when check=False and it fails)."""
+        H, W, ld = _img(X, "X")
+        if C is not None and (C.shape != X.shape or C.stride(0) != ld):
+            raise ValueError("C must match X's shape and pitch")
+        im = _Image(X.data_ptr(), C.data_ptr() if C is not None else None, H, W, ld, r)
+        t = ctypes.c_uint64()
+        st = _lib.hasf_serve_submit(self._h, ctypes.byref(im), ctypes.byref(t))
+        if st != HASF_OK:
+            if check:
+                raise HasfError(st, "hasf_serve_submit")
+            return st
+        self._keep[t.value] = (X, C)
+        return t.value
+
+    def submit_raw(self, ptr, H, W, ld, r, cptr=None):
+        """Queue a frame given by device pointer (the caller keeps it alive); returns (status, ticket)."""
+        im = _Image(ptr, cptr, H, W, ld, r)
+        t = ctypes.c_uint64()
+        st = _lib.hasf_serve_submit(self._h, ctypes.byref(im), ctypes.byref(t))
+        return st, t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        res = _Result()
+        st = _lib.hasf_serve_wait(self._h, ticket, timeout_ms, ctypes.byref(res))
+        if st == HASF_ETIMEDOUT:
+            return None
+        self._keep.pop(ticket, None)
+        if st != HASF_OK:
+            raise HasfError(st, "hasf_serve_wait")
+        return {"ticket": res.ticket, "submit_s": res.submit_s, "done_s": res.done_s,
+                "latency_ms": res.latency_ms}
+
+    def stats(self):
+        s = _Stats()
+        st = _lib.hasf_serve_stats(self._h, ctypes.byref(s))
+        if st != HASF_OK:
+            raise HasfError(st, "hasf_serve_stats")
+        return {k: getattr(s, k) for k, _ in _Stats._fields_}
+
+    def stop(self):
+        if getattr(self, "_h", None):
+            st = _lib.hasf_serve_stop(self._h)
+            self._h = None
+            self._keep.clear()
+            if st != HASF_OK:
+                raise HasfError(st, "hasf_serve_stop")
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

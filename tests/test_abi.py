@@ -64,3 +64,13 @@ def test_strerror():
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert lib.hasf_strerror(code)
     assert lib.hasf_strerror(-99) == b"unknown status"
+
+
+def test_serve_rejects_null_arguments():
+    hasf, lib = _lib()
+    t = ctypes.c_uint64()
+    assert lib.hasf_serve(None, None, None) == hasf.HASF_EINVAL
+    assert lib.hasf_serve_submit(None, None, ctypes.byref(t)) == hasf.HASF_EINVAL
+    assert lib.hasf_serve_wait(None, 1, 0, None) == hasf.HASF_EINVAL
+    assert lib.hasf_serve_stats(None, None) == hasf.HASF_EINVAL
+    assert lib.hasf_serve_stop(None) == hasf.HASF_EINVAL
