@@ -1,14 +1,31 @@
-"""Benchmark: HASF on 512x512 binary images, r = 5, batched vs plain.
+"""Benchmark: HASF on 512x512 binary images, r = 5: batched, plain and served.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--plain P]
+                [--serve-seconds S] [--mixed-seconds M] [--no-serve] [--no-cpu]
+python bench.py --only-edt      (the 4096x4096 exact EDT alone, for profiling)
 
 A step filters one batch of B synthetic 512x512 images (the 40-shape recipe
 with a 200-pixel constraint set each) in one persistent launch
 (hasf_filter_batch); the batch is first restored from a pristine device copy,
 since the filter works in place. Inputs are resident in HBM before timing.
-The plain path (one hasf_filter launch per image, serially) is timed on P
-frames for the batched-vs-plain ratio and per-frame latency. The CPU oracle
-is timed on a small sample of the same images (single thread).
+The value is the batched path's Mpixel/s over the K timed steps.
+
+Beside it, on the same GPU:
+* plain: one hasf_filter launch per image, serially, on P images (frames/s and
+  per-frame latency from HIP events);
+* served (hasf_serve): a Poisson stream of 512x512 r=5 frames at 2000
+  frames/s for S seconds (frames/s, p50/p99 latency from submission to
+  completion), a burst of 4096 such frames submitted at once (the server's
+  capacity), and the mixed stream -- Poisson 2000 frames/s for M seconds,
+  sides U[256,2048], r U{2..8}, the 12-disk recipe; its frames cycle through
+  64 distinct drawn frames of the schedule -- with the plain path timed on
+  those 64 frames;
+* edt: the exact squared EDT (hasf_edt_sq) of the 4096x4096 r=10 input, as
+  HBM GB/s against the 8 TB/s peak;
+* roofline: the batched filter kernel, bound by VALU integer lane operations
+  (instruction counts from the committed rocprofv3 counter summary);
+* cpu_baseline: the CPU oracle on a small sample of the 512x512 images
+  (single thread).
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -26,11 +43,13 @@ H = W = 512
 R = 5
 # int32 VALU lanes: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (ops/s)
 VALU_INT32_PEAK = 256 * 4 * 16 * 2.4e9
-# VALU instructions per 512x512 r=5 image of the filter kernel, from
-# rocprofv3 --pmc SQ_INSTS_VALU (profiles/filter_512x512_r5_counters.txt);
-# each wave64 VALU instruction is 64 lane-ops
-VALU_INSTS_PER_IMAGE = None
+HBM_PEAK = 8.0e12  # bytes/s
+# VALU instructions and HBM bytes per 512x512 r=5 image of the filter kernel,
+# from rocprofv3 --pmc (SQ_INSTS_VALU, FETCH_SIZE, WRITE_SIZE); each wave64
+# VALU instruction is 64 lane-ops
 PROFILE_COUNTS = os.path.join(ROOT, "profiles", "filter_512x512_r5_counters.json")
+# exact EDT: 1 byte read + 4 bytes written per pixel
+EDT_BYTES_PER_PX = 5
 
 
 def parse():
@@ -42,8 +61,18 @@ def parse():
     ap.add_argument("--distinct", type=int, default=64)
     ap.add_argument("--plain", type=int, default=64)
     ap.add_argument("--cpu-sample", type=int, default=12)
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--mixed-seconds", type=float, default=1.0)
+    ap.add_argument("--rate", type=float, default=2000.0)
+    ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only-edt", action="store_true")
     return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
 
 
 def make_inputs(n_distinct):
@@ -58,6 +87,181 @@ def make_inputs(n_distinct):
     return np.stack(Xs), np.stack(Cs)
 
 
+def bench_edt(ctx, reps=20):
+    """Exact squared EDT of the 4096x4096 input, HBM GB/s."""
+    import torch
+    from paper_1603_09337_amd import synth
+    X, _, _ = synth.workload_large()
+    Hn, Wn = X.shape
+    x = torch.from_numpy(X).cuda()
+    d2 = torch.empty((Hn, Wn), dtype=torch.int32, device="cuda")
+    for _ in range(3):
+        ctx.edt_sq(x, True, d2)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        ctx.edt_sq(x, True, d2)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    bytes_ = EDT_BYTES_PER_PX * Hn * Wn
+    return {"bound": "hbm", "achieved": round(bytes_ / t / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": round(bytes_ / t / HBM_PEAK, 4), "traffic": None, "us_per_call": round(t * 1e6, 1),
+            "workload": "hasf_edt_sq 4096x4096, border is feature (the 4096x4096 r=10 input)",
+            "bytes_per_call": bytes_}
+
+
+def run_stream(srv, frames, arrivals):
+    """Submit frames[k] at arrivals[k] seconds (host clock) and wait for all."""
+    t0 = time.perf_counter()
+    tickets = []
+    for (x, c, r), ta in zip(frames, arrivals):
+        while True:
+            dt = ta - (time.perf_counter() - t0)
+            if dt <= 0:
+                break
+            if dt > 1e-3:
+                time.sleep(dt - 5e-4)
+        tickets.append(srv.submit(x, c, r))
+    t_sub = time.perf_counter() - t0
+    res = [srv.wait(t, 120000) for t in tickets]
+    if any(r is None for r in res):
+        raise RuntimeError("served frame did not complete in 120 s")
+    st = srv.stats()
+    return st, res, t_sub
+
+
+def stream_summary(st, res, npx, t_sub, rate=None):
+    import numpy as np
+    lat = np.array([r["latency_ms"] for r in res])
+    t_first = min(r["submit_s"] for r in res)
+    t_last = max(r["done_s"] for r in res)
+    out = {"frames": len(res), "frames_per_s": round(len(res) / (t_last - t_first), 1),
+           "Mpixel_per_s": round(npx / (t_last - t_first) / 1e6, 2),
+           "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+           "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
+           "latency_ms_max": round(float(lat.max()), 3),
+           "kernel_launches": int(st["kernel_launches"]),
+           "frames_per_launch": round(float(st["frames_per_launch"]), 2),
+           "pool_peak_MiB": round(st["pool_peak_bytes"] / 2**20, 1)}
+    if rate is not None:
+        out["offered_frames_per_s"] = rate
+        out["submit_seconds"] = round(t_sub, 3)
+    return out
+
+
+def bench_served(ctx, a, src, Cd):
+    """Served streams: 512x512 Poisson, 512x512 burst, mixed-size Poisson."""
+    import numpy as np
+    import torch
+    from paper_1603_09337_amd import hasf, synth
+    out = {}
+    rng = np.random.Generator(np.random.PCG64(synth.SEED_STREAM + 1))
+
+    # 512x512 r=5 at the offered rate
+    gaps = rng.exponential(1.0 / a.rate, size=int(a.rate * a.serve_seconds * 1.5) + 16)
+    arr = np.cumsum(gaps)
+    arr = arr[arr < a.serve_seconds]
+    n = len(arr)
+    D = src.shape[0]
+    X = src[torch.arange(n, device=src.device) % D].clone()
+    torch.cuda.synchronize()
+    frames = [(X[k], Cd[k % D], R) for k in range(n)]
+    srv = hasf.Server(ctx, lanes=a.lanes)
+    # warm the server's lanes
+    w = src[:8].clone()
+    torch.cuda.synchronize()
+    for t in [srv.submit(w[k], Cd[k], R) for k in range(8)]:
+        srv.wait(t, 60000)
+    srv.stop()
+    srv = hasf.Server(ctx, lanes=a.lanes)
+    log("served 512x512 stream: %d frames" % n)
+    st, res, t_sub = run_stream(srv, frames, arr)
+    srv.stop()
+    out["stream_512"] = stream_summary(st, res, n * H * W, t_sub, a.rate)
+    out["stream_512"]["workload"] = "Poisson %g frames/s for %g s, 512x512 r=5, C = 200 pixels" % (
+        a.rate, a.serve_seconds)
+    del X, frames
+
+    # burst: the server's capacity on 512x512 r=5
+    nb = 4096
+    Xb = src[torch.arange(nb, device=src.device) % D].clone()
+    torch.cuda.synchronize()
+    srv = hasf.Server(ctx, lanes=a.lanes)
+    log("served 512x512 burst: %d frames" % nb)
+    st, res, t_sub = run_stream(srv, [(Xb[k], Cd[k % D], R) for k in range(nb)], np.zeros(nb))
+    srv.stop()
+    out["burst_512"] = stream_summary(st, res, nb * H * W, t_sub)
+    out["burst_512"]["workload"] = "4096 frames 512x512 r=5 submitted at once"
+    del Xb
+
+    # mixed sizes
+    sched = synth.stream_schedule(rate=a.rate, seconds=a.mixed_seconds)
+    nbank = min(64, len(sched))
+    bank = []
+    for k in range(nbank):
+        _, Hk, Wk, rk, fs = sched[k]
+        bank.append((torch.from_numpy(synth.stream_frame(Hk, Wk, fs)).cuda(), rk))
+    offs, tot = [], 0
+    for k in range(len(sched)):
+        Hk, Wk = bank[k % nbank][0].shape
+        offs.append(tot)
+        tot += (Hk * Wk + 255) // 256 * 256
+    flat = torch.empty(tot, dtype=torch.uint8, device="cuda")
+    frames, npx = [], 0
+    for k in range(len(sched)):
+        b, rk = bank[k % nbank]
+        Hk, Wk = b.shape
+        v = flat[offs[k]:offs[k] + Hk * Wk].view(Hk, Wk)
+        v.copy_(b)
+        frames.append((v, None, rk))
+        npx += Hk * Wk
+    torch.cuda.synchronize()
+    srv = hasf.Server(ctx, lanes=a.lanes)
+    log("served mixed stream: %d frames, %.2f Gpx" % (len(frames), npx / 1e9))
+    st, res, t_sub = run_stream(srv, frames, [s[0] for s in sched])
+    srv.stop()
+    mixed = stream_summary(st, res, npx, t_sub, a.rate)
+    mixed["workload"] = ("Poisson %g frames/s for %g s, H and W U[256,2048], r U{2..8}, 12-disk recipe "
+                         "(frames cycle through %d drawn frames)" % (a.rate, a.mixed_seconds, nbank))
+    # latency by frame size (pixels)
+    px = np.array([f[0].shape[0] * f[0].shape[1] for f in frames])
+    lat = np.array([r["latency_ms"] for r in res])
+    buckets = {}
+    for lo, hi, name in [(0, 2**19, "<=0.5Mpx"), (2**19, 2**21, "0.5-2Mpx"), (2**21, 2**23, ">2Mpx")]:
+        m = (px > lo) & (px <= hi)
+        if m.any():
+            buckets[name] = {"frames": int(m.sum()), "latency_ms_p50": round(float(np.percentile(lat[m], 50)), 2),
+                             "latency_ms_p99": round(float(np.percentile(lat[m], 99)), 2)}
+    mixed["by_size"] = buckets
+    out["stream_mixed"] = mixed
+    del frames, flat
+
+    # plain path on the mixed stream's distinct frames
+    stream = torch.cuda.current_stream()
+    work = [(b.clone(), rk) for b, rk in bank]
+    torch.cuda.synchronize()
+    ev = []
+    t0 = time.perf_counter()
+    for x, rk in work:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.filter(x, None, rk)
+        e1.record(stream)
+        ev.append((e0, e1))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pl = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    ppx = sum(x.shape[0] * x.shape[1] for x, _ in work)
+    out["plain_mixed"] = {"frames": nbank, "frames_per_s": round(nbank / (t1 - t0), 2),
+                          "Mpixel_per_s": round(ppx / (t1 - t0) / 1e6, 2),
+                          "latency_ms_p50": round(float(np.percentile(pl, 50)), 2),
+                          "latency_ms_p99": round(float(np.percentile(pl, 99)), 2)}
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -70,6 +274,9 @@ def main():
 
     dev = torch.device("cuda:0")
     ctx = hasf.Context(0)
+    if a.only_edt:
+        print(json.dumps({"edt": bench_edt(ctx, reps=a.steps)}), flush=True)
+        return
     Xs, Cs = make_inputs(a.distinct)
     B = a.batch
     idx = np.arange(B) % a.distinct
@@ -87,6 +294,7 @@ def main():
         if kernel_events is not None:
             kernel_events[1].record(stream)
 
+    log("batched: %d steps of %d images" % (a.steps, B))
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
@@ -102,10 +310,8 @@ def main():
     frames = B * a.steps
     px = frames * H * W
 
-    # correctness spot check of the last batch against the first pass (bitwise
-    # identical runs) is done in the tests; here only the throughput is measured
-
     # plain path: one launch per frame
+    log("plain: %d frames" % a.plain)
     lat = []
     pw = src[: a.plain].clone()
     pc = Cd[: a.plain]
@@ -143,10 +349,18 @@ def main():
                 "frac": round(ach / peak, 4), "traffic": traffic,
                 "kernel": "hasf_filter_kernel", "ops": "int32 VALU lane-ops"}
 
+    log("edt 4096x4096")
+    edt = bench_edt(ctx)
+
+    served = None
+    if not a.no_serve:
+        served = bench_served(ctx, a, src, Cd)
+
     cpu = None
     if not a.no_cpu and a.cpu_sample > 0:
         import oracle
         n = a.cpu_sample
+        log("cpu oracle: %d frames" % n)
         tc0 = time.perf_counter()
         for k in range(n):
             oracle.hasf(Xs[k % a.distinct], Cs[k % a.distinct], R)
@@ -176,6 +390,9 @@ def main():
                   "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 3), "frames": a.plain},
         "batched_over_plain": round((frames / wall) / plain_fps, 2),
         "batch_kernel_ms": round(float(np.mean(kern_ms)), 3),
+        "served": served,
+        "served_over_plain": (round(served["stream_512"]["frames_per_s"] / plain_fps, 2) if served else None),
+        "edt": edt,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -153,26 +153,34 @@ hasf_status hasf_filter_batch(hasf_ctx* ctx, const hasf_image* imgs, int n);
 
 /*
  * Served stream (continuous batching). hasf_serve starts a server on ctx's
- * device: a persistent kernel whose idle workgroups take frames as soon as
- * they are published, and a host dispatcher thread that admits submitted
- * frames in arrival order when their scratch memory fits in the server's
- * device pool (admission by HBM footprint), publishes them to the kernel and
- * retires them as they complete. Frames that arrive while others are being
- * filtered start on the next free workgroup, so their work overlaps on the
- * device; each frame's result equals hasf_filter on that frame alone.
+ * device: a host dispatcher thread and a few launch lanes (streams of their
+ * own, each with at most one launch of the batched filter kernel in flight).
+ * Submitted frames wait in arrival order; whenever a lane is free, the
+ * dispatcher admits the waiting frames whose scratch memory (bit planes and
+ * level entries, kept on the device) fits in the server's device pool --
+ * admission by HBM footprint -- and launches them as one batch. Frames that
+ * arrive while others are being filtered go into the next free lane, so their
+ * work overlaps on the device with the frames already there. A frame is
+ * completed, and its scratch returned to the pool, as soon as the kernel has
+ * finished it, not when its launch ends. Each frame's result equals
+ * hasf_filter on that frame alone.
  *
  * Frames are device-resident: img->X (and img->C) are DEVICE pointers, filtered
  * in place; the caller keeps them alive and untouched until the frame's
- * hasf_serve_wait has returned. While a server runs, do not synchronise the
- * whole device (hipDeviceSynchronize): its kernel only returns when the server
- * stops or has been idle for opts->idle_exit_ms.
+ * hasf_serve_wait has returned. Frames must not overlap one another.
  */
+#define HASF_SERVE_LANES_MAX 16
+/* opts.flags bit: the persistent polling kernel (workgroups that stay resident
+ * and claim frames from a host-mapped ring). Switched off: hasf_serve returns
+ * HASF_EINTERNAL when it is set. */
+#define HASF_SERVE_PERSISTENT 1u
+
 typedef struct {
     size_t pool_bytes;     /* device memory for frame scratch; 0 = the context's hbm_budget */
-    int ring_slots;        /* frames published at once (0 = 4096) */
-    int max_pending;       /* submitted but not admitted; beyond it submit returns HASF_EAGAIN (0 = 1 << 20) */
-    int idle_exit_ms;      /* the kernel exits after this long without work and is relaunched on demand (0 = 2000) */
-    unsigned flags;        /* reserved, must be 0 */
+    int lanes;             /* launches in flight at once, 1..HASF_SERVE_LANES_MAX (0 = 4) */
+    int max_batch;         /* frames per launch (0 = 1024) */
+    int max_pending;       /* submitted but not yet admitted; beyond it submit returns HASF_EAGAIN (0 = 1 << 20) */
+    unsigned flags;        /* 0 (HASF_SERVE_PERSISTENT is switched off) */
 } hasf_serve_opts;
 
 typedef struct hasf_server hasf_server;
@@ -193,6 +201,8 @@ typedef struct {
     double mpixel_per_s;
     size_t pool_bytes, pool_peak_bytes;
     uint64_t kernel_launches;
+    double frames_per_launch;        /* mean batch size of the launches */
+    uint64_t batch_max;              /* largest batch launched */
 } hasf_stats;
 
 hasf_status hasf_serve(hasf_ctx* ctx, const hasf_serve_opts* opts, hasf_server** out);

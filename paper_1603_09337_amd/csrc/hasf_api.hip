@@ -10,7 +10,7 @@
 
 namespace hasf_detail {
 hipError_t launch_filter(const ImgDesc* d_desc, int n, int* d_next, int grid, size_t lds_bytes,
-                         hipStream_t stream);
+                         hipStream_t stream, unsigned* done);
 int filter_block();
 size_t edt_scratch_bytes(int H, int W);
 hipError_t launch_edt(const uint8_t* F, int H, int W, long long ld, int frame, int invert, uint32_t* d2,
@@ -103,6 +103,11 @@ struct Layout {
 };
 
 }  // namespace
+
+namespace hasf_detail {
+// error text for ctx and the calling thread (used by the server as well)
+void record_error(hasf_ctx* ctx, const char* msg) { set_err(ctx, "%s", msg); }
+}  // namespace hasf_detail
 
 extern "C" {
 
@@ -343,7 +348,7 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
         return dev_fail(ctx, e, "hipStreamSynchronize(descriptors)");
     const int occ = std::max(1, filter_occupancy(lds_need));
     const int grid = std::min(n, ctx->num_cu * occ);
-    e = launch_filter((const ImgDesc*)(base + 256), n, (int*)base, grid, lds_need, ctx->stream);
+    e = launch_filter((const ImgDesc*)(base + 256), n, (int*)base, grid, lds_need, ctx->stream, nullptr);
     if (e != hipSuccess)
         return dev_fail(ctx, e, "hasf_filter launch");
     return HASF_OK;

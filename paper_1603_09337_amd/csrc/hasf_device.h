@@ -483,6 +483,12 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
         if (*chg <= round_start)
             break;
     }
+    // The skip decisions after the last executed pass read prod and chg with
+    // no barrier behind them. The caller's next activation writes prod: a
+    // wave that got there first would make a slower wave see a new serial,
+    // run a pass the others skipped and leave the workgroup's barriers out
+    // of step. Every wave finishes its decisions before anyone goes on.
+    __syncthreads();
 }
 
 }  // namespace hasf_dev

@@ -1,6 +1,6 @@
 // Persistent per-image HASF kernel for gfx950.
 //
-// One workgroup (1024 threads, 16 wave64s) owns one image at a time and runs
+// One workgroup (512 threads, 8 wave64s) owns one image at a time and runs
 // the whole radius loop of the filter on it (Sec. 2: HASF = HF_r o HC_r o ...
 // o HF_1 o HC_1), so every synchronisation of the level/round/subfield
 // schedule is a workgroup barrier. Workgroups claim images from a queue
@@ -21,6 +21,8 @@
 // the pixels first reached by V_a shifted by +-b have squared distance
 // a^2 + b^2 exactly. This is evaluated on whole words, per level, and
 // produces the candidate bits of each level directly as (word, mask) entries.
+#include <atomic>
+
 #include "hasf_device.h"
 
 using namespace hasf_dev;
@@ -273,9 +275,11 @@ __device__ __attribute__((noinline)) void run_image(const ImgDesc* __restrict__ 
 
 }  // namespace
 
-// Each workgroup claims images in queue order until the queue is empty.
+// Each workgroup claims images in queue order until the queue is empty. When
+// `done` is given (host-mapped memory), done[q] becomes 1 once image q's
+// result is in memory, so the host can hand it out before the launch ends.
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void hasf_filter_kernel(
-    const ImgDesc* __restrict__ desc, int n, int* __restrict__ next)
+    const ImgDesc* __restrict__ desc, int n, int* __restrict__ next, unsigned* done)
 {
     extern __shared__ uint64_t smem[];
     __shared__ unsigned cnt[HASF_LEVELS_MAX];
@@ -293,94 +297,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
             run_image<true>(desc + img, smem, (lds_u32*)cnt, (lds_i32*)ctl);
         else
             run_image<false>(desc + img, smem, (lds_u32*)cnt, (lds_i32*)ctl);
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Served stream: a persistent kernel whose workgroups claim frames from a ring
-// of descriptors that the host publishes while the kernel runs.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long load_sys(const unsigned long long* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
-__device__ __forceinline__ int load_sys_i(const int* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
-// ring: host-pinned descriptors [cap], published count `tail`, `stop` flag and
-// per-slot completion words `done` (the frame's sequence number + 1);
-// `head` (device memory) counts claimed frames; `dev_desc` [cap] holds the
-// device-side copy of each claimed descriptor. A workgroup exits when the
-// host has set `stop` and every published frame is claimed, or after
-// `idle_limit` wall-clock ticks (100 MHz) without work.
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void hasf_serve_kernel(
-    const ImgDesc* ring, const unsigned long long* tail, const int* stop, int* done,
-    unsigned long long* __restrict__ head, ImgDesc* __restrict__ dev_desc, int cap,
-    unsigned long long idle_limit)
-{
-    extern __shared__ uint64_t smem[];
-    __shared__ unsigned cnt[HASF_LEVELS_MAX];
-    __shared__ int ctl[CTL_WORDS];
-    __shared__ long long s_idx;
-    for (;;) {
-        if (threadIdx.x == 0) {
-            long long idx = -1;
-            const unsigned long long t0 = wall_clock64();
-            int backoff = 1;  // s_sleep calls between polls of host memory, doubled while idle
-            for (;;) {
-                const unsigned long long t = load_sys(tail);
-                const unsigned long long h = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (h < t) {
-                    unsigned long long exp = h;
-                    if (__hip_atomic_compare_exchange_strong(head, &exp, h + 1, __ATOMIC_RELAXED,
-                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                        idx = (long long)h;
-                        break;
-                    }
-                    continue;
-                }
-                if (load_sys_i(stop))
-                    break;
-                if (wall_clock64() - t0 > idle_limit)
-                    break;
-                for (int k = 0; k < backoff; ++k)
-                    __builtin_amdgcn_s_sleep(127);
-                backoff = min(backoff * 2, 32);
+        if (done) {
+            __threadfence();  // each thread's stores of the image reach device scope
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                // and the whole image is visible to the host and to copy
+                // engines before its completion word
+                __threadfence_system();
+                __hip_atomic_store(done + img, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
             }
-            if (idx >= 0) {
-                // device-side copy of the descriptor (read once from host memory)
-                const int slot = (int)(idx % cap);
-                const unsigned* src = (const unsigned*)(ring + slot);
-                unsigned* dst = (unsigned*)(dev_desc + slot);
-                for (int k = 0; k < (int)(sizeof(ImgDesc) / 4); ++k)
-                    dst[k] = __hip_atomic_load(src + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                __threadfence();
-            }
-            s_idx = idx;
         }
         __syncthreads();
-        const long long idx = s_idx;
-        __syncthreads();
-        if (idx < 0)
-            break;
-        const int slot = (int)(idx % cap);
-        const ImgDesc* dp = dev_desc + slot;
-        if (dp->lds)
-            run_image<true>(dp, smem, (lds_u32*)cnt, (lds_i32*)ctl);
-        else
-            run_image<false>(dp, smem, (lds_u32*)cnt, (lds_i32*)ctl);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            // results in device memory become visible to the host and the copy
-            // engines before the completion word
-            __threadfence_system();
-            __hip_atomic_store(done + slot, (int)(idx & 0x3FFFFFFF) + 1, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_SYSTEM);
-        }
     }
 }
 
@@ -392,17 +319,18 @@ namespace hasf_detail {
 int filter_block() { return BLOCK; }
 
 hipError_t launch_filter(const ImgDesc* d_desc, int n, int* d_next, int grid, size_t lds_bytes,
-                         hipStream_t stream)
+                         hipStream_t stream, unsigned* done)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
+    // launched from the caller's thread and from a server's dispatcher thread
+    static std::atomic<bool> attr_set{false};
+    if (!attr_set.load(std::memory_order_acquire)) {
         hipError_t e = hipFuncSetAttribute((const void*)hasf_filter_kernel,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
         if (e != hipSuccess)
             return e;
-        attr_set = true;
+        attr_set.store(true, std::memory_order_release);
     }
-    hipLaunchKernelGGL(hasf_filter_kernel, dim3(grid), dim3(BLOCK), lds_bytes, stream, d_desc, n, d_next);
+    hipLaunchKernelGGL(hasf_filter_kernel, dim3(grid), dim3(BLOCK), lds_bytes, stream, d_desc, n, d_next, done);
     return hipGetLastError();
 }
 
@@ -422,33 +350,3 @@ int filter_occupancy(size_t lds_bytes)
 
 }  // namespace hasf_detail
 
-namespace hasf_detail {
-
-hipError_t launch_serve(const ImgDesc* ring, const unsigned long long* tail, const int* stop, int* done,
-                        unsigned long long* head, ImgDesc* dev_desc, int cap, unsigned long long idle_limit,
-                        int grid, size_t lds_bytes, hipStream_t stream)
-{
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)hasf_serve_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
-        if (e != hipSuccess)
-            return e;
-        attr_set = true;
-    }
-    hipLaunchKernelGGL(hasf_serve_kernel, dim3(grid), dim3(BLOCK), lds_bytes, stream, ring, tail, stop, done, head,
-                       dev_desc, cap, idle_limit);
-    return hipGetLastError();
-}
-
-int serve_occupancy(size_t lds_bytes)
-{
-    int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, hasf_serve_kernel, BLOCK, lds_bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return 1;
-    }
-    return blocks;
-}
-
-}  // namespace hasf_detail

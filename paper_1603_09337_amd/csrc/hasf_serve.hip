@@ -1,18 +1,20 @@
-// Served stream: host dispatcher of the persistent filter kernel.
+// Served stream: continuous batching of frames over launch lanes.
 //
-// Submitted frames wait in arrival order until their scratch fits in the
-// server's device pool (admission by HBM footprint) and a ring slot is free;
-// the dispatcher then writes the frame's descriptor into a ring in pinned
-// host memory and advances the published count, which the kernel's idle
-// workgroups poll. A workgroup that finishes a frame stores the frame's
-// sequence number in the slot's completion word; the dispatcher sees it,
-// stamps the completion time, frees the scratch and wakes waiters. The kernel
-// exits when stopped or after an idle period; the dispatcher relaunches it
-// whenever published frames are outstanding and it is not running.
+// Submitted frames wait in arrival order. A host dispatcher thread owns a few
+// lanes, each a stream with at most one launch of the persistent filter
+// kernel in flight. Whenever a lane is free it takes the waiting frames, in
+// arrival order, whose scratch (bit planes and level entries) still fits in
+// the server's device pool -- admission by HBM footprint -- up to a per-launch
+// cap, and launches them as one cost-ordered batch. Frames that arrive while
+// other launches run go into the next free lane, so their work overlaps on
+// the device with the frames already there. The kernel sets a completion word
+// in host-mapped memory after each frame, so a frame is handed out, and its
+// scratch returned to the pool, as soon as it is done, not when its launch
+// ends.
 #include <algorithm>
-#include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -25,10 +27,10 @@
 #include "hasf_common.h"
 
 namespace hasf_detail {
-hipError_t launch_serve(const ImgDesc* ring, const unsigned long long* tail, const int* stop, int* done,
-                        unsigned long long* head, ImgDesc* dev_desc, int cap, unsigned long long idle_limit,
-                        int grid, size_t lds_bytes, hipStream_t stream);
-int serve_occupancy(size_t lds_bytes);
+hipError_t launch_filter(const ImgDesc* d_desc, int n, int* d_next, int grid, size_t lds_bytes,
+                         hipStream_t stream, unsigned* done);
+int filter_occupancy(size_t lds_bytes);
+void record_error(hasf_ctx* ctx, const char* msg);
 }  // namespace hasf_detail
 
 using namespace hasf_detail;
@@ -49,7 +51,8 @@ struct Pool {
     {
         size = n;
         free_.clear();
-        free_[0] = n;
+        if (n)
+            free_[0] = n;
         used = peak = 0;
     }
     bool alloc(size_t n, size_t* off)
@@ -89,64 +92,145 @@ struct Pool {
 };
 
 struct Frame {
-    uint64_t ticket;
-    hasf_image img;
-    ImageLayout lay;
-    size_t off = 0;
-    int slot = -1;
-    unsigned long long seq = 0;
+    uint64_t ticket = 0;
+    hasf_image img{};
+    ImageLayout lay{};
+    double cost = 0;
+    size_t off = 0;  // pool offset in bytes
     double t_submit = 0, t_done = 0;
     int status = HASF_OK;
     bool done = false;
 };
 
+// one stream with at most one launch in flight
+struct Lane {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    char* d_meta = nullptr;      // device: [queue counter | descriptors]
+    char* h_meta = nullptr;      // pinned staging of d_meta
+    unsigned* h_done = nullptr;  // host-mapped completion words, one per queue position
+    unsigned* d_done = nullptr;  // the same words as the kernel addresses them
+    std::vector<Frame*> frames;  // queue position -> frame (nullptr once retired)
+    bool busy = false;
+};
+
+double frame_cost(const hasf_image& im)
+{
+    double lv = 0;
+    for (int i = 1; i <= im.r; ++i)
+        lv += hasf_levels(i) + 1;
+    return (double)im.H * im.W * (lv + 1);
+}
+
 }  // namespace
 
 struct hasf_server {
     hasf_ctx* ctx = nullptr;
-    hipStream_t stream = nullptr;
-    // pinned host memory (mapped)
-    ImgDesc* ring = nullptr;
-    unsigned long long* tail = nullptr;
-    int* stop = nullptr;
-    int* done = nullptr;
-    // device pointers of the pinned memory
-    ImgDesc* d_ring = nullptr;
-    unsigned long long* d_tail = nullptr;
-    int* d_stop = nullptr;
-    int* d_done = nullptr;
-    // device memory
-    unsigned long long* head = nullptr;
-    ImgDesc* dev_desc = nullptr;
     char* pool_mem = nullptr;
     Pool pool;
-    int cap = 0;
+    std::vector<Lane> lanes;
+    int max_batch = 0;
     int max_pending = 0;
-    unsigned long long idle_ticks = 0;
-    size_t lds_cap = 0, lds_launch = 0;
-    int grid = 0;
+    size_t lds_cap = 0;
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Frame*> pending;
-    std::vector<Frame*> inflight;
-    std::vector<Frame*> slot_frame;
+    size_t in_flight = 0;
     std::unordered_map<uint64_t, Frame*> frames;
     uint64_t next_ticket = 1;
-    unsigned long long published = 0;
     bool stopping = false;
-    bool kernel_running = false;
     int fatal = HASF_OK;
     char err[256] = "";
     std::thread worker;
 
     // stats
-    uint64_t submitted = 0, completed = 0, rejected = 0, launches = 0;
+    uint64_t submitted = 0, completed = 0, rejected = 0, launches = 0, launched_frames = 0;
+    int batch_max = 0;
     double t_first = 0, t_last = 0, px_done = 0;
     std::vector<double> lat_ms;
 };
 
 namespace {
+
+void retire(hasf_server* s, Frame* f, double t, int status)
+{
+    f->t_done = t;
+    f->status = status;
+    f->done = true;
+    s->pool.release(f->off / 256, f->lay.total() / 256);
+    --s->in_flight;
+    if (status == HASF_OK) {
+        ++s->completed;
+        s->t_last = t;
+        s->px_done += (double)f->img.H * f->img.W;
+        s->lat_ms.push_back((t - f->t_submit) * 1e3);
+    }
+}
+
+// Launches the waiting frames that fit on `ln`; false if none fits now.
+bool launch_lane(hasf_server* s, Lane& ln)
+{
+    std::vector<Frame*> take;
+    while (!s->pending.empty() && (int)take.size() < s->max_batch) {
+        Frame* f = s->pending.front();
+        size_t off = 0;
+        if (!s->pool.alloc(f->lay.total() / 256, &off))
+            break;  // HBM footprint: wait until frames on the device finish
+        f->off = off * 256;
+        s->pending.pop_front();
+        take.push_back(f);
+    }
+    if (take.empty())
+        return false;
+    // queue order of the launch: decreasing cost (largest first)
+    std::stable_sort(take.begin(), take.end(), [](const Frame* a, const Frame* b) { return a->cost > b->cost; });
+    const int n = (int)take.size();
+    ImgDesc* desc = (ImgDesc*)(ln.h_meta + 256);
+    size_t lds_need = 0;
+    for (int q = 0; q < n; ++q) {
+        const Frame* f = take[q];
+        ImgDesc& d = desc[q];
+        d.X = f->img.X;
+        d.C = f->img.C;
+        d.ld = f->img.ld;
+        d.H = f->img.H;
+        d.W = f->img.W;
+        d.r = f->img.r;
+        d.lds = f->lay.lds ? 1 : 0;
+        lds_need = std::max(lds_need, f->lay.lds_bytes);
+        char* base = s->pool_mem + f->off;
+        d.gplanes = (uint64_t*)base;
+        d.ent_idx = (uint32_t*)(base + f->lay.planes_bytes);
+        d.ent_msk = (uint64_t*)(base + f->lay.planes_bytes + f->lay.idx_bytes);
+        ln.h_done[q] = 0;
+    }
+    std::memset(ln.h_meta, 0, 256);  // the launch's queue counter starts at 0
+    ln.frames = take;
+    ln.busy = true;
+    s->in_flight += n;
+    ++s->launches;
+    s->launched_frames += n;
+    s->batch_max = std::max(s->batch_max, n);
+
+    const int occ = std::max(1, filter_occupancy(lds_need));
+    const int grid = std::min(n, s->ctx->num_cu * occ);
+    // h_meta is pinned and not rewritten before this lane's launch has ended,
+    // so the copy may run after this call returns
+    hipError_t e = hipMemcpyAsync(ln.d_meta, ln.h_meta, 256 + sizeof(ImgDesc) * (size_t)n, hipMemcpyHostToDevice,
+                                  ln.stream);
+    if (e == hipSuccess)
+        e = launch_filter((const ImgDesc*)(ln.d_meta + 256), n, (int*)ln.d_meta, grid, lds_need, ln.stream,
+                          ln.d_done);
+    if (e == hipSuccess)
+        e = hipEventRecord(ln.ev, ln.stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        s->fatal = HASF_EDEVICE;
+        snprintf(s->err, sizeof s->err, "serve launch: %s", hipGetErrorString(e));
+    }
+    return true;
+}
 
 void serve_loop(hasf_server* s)
 {
@@ -154,111 +238,93 @@ void serve_loop(hasf_server* s)
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         bool progress = false;
-        // admit in arrival order while memory and ring slots allow
-        while (!s->pending.empty() && s->fatal == HASF_OK) {
-            Frame* f = s->pending.front();
-            const int slot = (int)(s->published % (unsigned long long)s->cap);
-            if (s->slot_frame[slot])
-                break;  // ring full
-            size_t off = 0;
-            if (!s->pool.alloc(f->lay.total() / 256, &off))
-                break;  // HBM budget: wait for frames to complete
-            off *= 256;
-            s->pending.pop_front();
-            f->off = off;
-            f->slot = slot;
-            f->seq = s->published;
-            ImgDesc d;
-            d.X = f->img.X;
-            d.C = f->img.C;
-            d.ld = f->img.ld;
-            d.H = f->img.H;
-            d.W = f->img.W;
-            d.r = f->img.r;
-            d.lds = f->lay.lds ? 1 : 0;
-            char* base = s->pool_mem + off;
-            d.gplanes = (uint64_t*)base;
-            d.ent_idx = (uint32_t*)(base + f->lay.planes_bytes);
-            d.ent_msk = (uint64_t*)(base + f->lay.planes_bytes + f->lay.idx_bytes);
-            std::memcpy((void*)(s->ring + slot), &d, sizeof d);
-            __atomic_store_n(s->done + slot, 0, __ATOMIC_RELAXED);
-            s->slot_frame[slot] = f;
-            s->inflight.push_back(f);
-            ++s->published;
-            __atomic_store_n(s->tail, s->published, __ATOMIC_RELEASE);
-            progress = true;
-        }
-        // (re)start the kernel when published frames are outstanding
-        if (!s->inflight.empty() && s->fatal == HASF_OK) {
-            if (s->kernel_running && hipStreamQuery(s->stream) == hipSuccess)
-                s->kernel_running = false;
-            if (!s->kernel_running) {
-                hipError_t e = launch_serve(s->d_ring, s->d_tail, s->d_stop, s->d_done, s->head, s->dev_desc, s->cap,
-                                            s->idle_ticks, s->grid, s->lds_launch, s->stream);
-                if (e != hipSuccess) {
-                    s->fatal = HASF_EDEVICE;
-                    snprintf(s->err, sizeof s->err, "serve kernel launch: %s", hipGetErrorString(e));
-                } else {
-                    s->kernel_running = true;
-                    ++s->launches;
+        // retire: frames whose completion word is set, then ended launches
+        for (Lane& ln : s->lanes) {
+            if (!ln.busy)
+                continue;
+            const double t = now_s();
+            for (size_t q = 0; q < ln.frames.size(); ++q) {
+                Frame* f = ln.frames[q];
+                if (f && __atomic_load_n(ln.h_done + q, __ATOMIC_ACQUIRE)) {
+                    retire(s, f, t, HASF_OK);
+                    ln.frames[q] = nullptr;
+                    progress = true;
                 }
             }
-        }
-        // retire completed frames
-        for (size_t k = 0; k < s->inflight.size();) {
-            Frame* f = s->inflight[k];
-            const int w = __atomic_load_n(s->done + f->slot, __ATOMIC_ACQUIRE);
-            if (w == (int)(f->seq & 0x3FFFFFFFull) + 1) {
-                f->t_done = now_s();
-                f->done = true;
-                s->pool.release(f->off / 256, f->lay.total() / 256);
-                s->slot_frame[f->slot] = nullptr;
-                s->inflight[k] = s->inflight.back();
-                s->inflight.pop_back();
-                ++s->completed;
-                s->t_last = f->t_done;
-                s->px_done += (double)f->img.H * f->img.W;
-                s->lat_ms.push_back((f->t_done - f->t_submit) * 1e3);
-                progress = true;
-            } else {
-                ++k;
+            const hipError_t e = hipEventQuery(ln.ev);
+            if (e == hipErrorNotReady)
+                continue;
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                if (s->fatal == HASF_OK) {
+                    s->fatal = HASF_EDEVICE;
+                    snprintf(s->err, sizeof s->err, "serve kernel: %s", hipGetErrorString(e));
+                }
             }
+            // the launch has ended: a frame without its completion word failed
+            const double t2 = now_s();
+            for (size_t q = 0; q < ln.frames.size(); ++q) {
+                if (Frame* f = ln.frames[q]) {
+                    const bool ok = e == hipSuccess && __atomic_load_n(ln.h_done + q, __ATOMIC_ACQUIRE);
+                    retire(s, f, t2, ok ? HASF_OK : (e == hipSuccess ? HASF_EINTERNAL : HASF_EDEVICE));
+                }
+            }
+            ln.frames.clear();
+            ln.busy = false;
+            progress = true;
         }
-        if (s->fatal != HASF_OK) {
-            // fail everything still queued
+        // launch waiting frames on free lanes
+        if (s->fatal == HASF_OK) {
+            for (Lane& ln : s->lanes) {
+                if (s->pending.empty())
+                    break;
+                if (!ln.busy && launch_lane(s, ln))
+                    progress = true;
+            }
+        } else if (!s->pending.empty()) {
+            const double t = now_s();
             for (Frame* f : s->pending) {
                 f->status = s->fatal;
+                f->t_done = t;
                 f->done = true;
             }
             s->pending.clear();
-            if (!s->inflight.empty() && !s->kernel_running) {
-                for (Frame* f : s->inflight) {
-                    f->status = s->fatal;
-                    f->done = true;
-                    s->slot_frame[f->slot] = nullptr;
-                }
-                s->inflight.clear();
-            }
+            progress = true;
         }
         if (progress)
             s->cv_done.notify_all();
-        if (s->stopping && s->pending.empty() && s->inflight.empty())
+        if (s->stopping && s->pending.empty() && s->in_flight == 0)
             break;
-        if (s->pending.empty() && s->inflight.empty()) {
+        if (s->pending.empty() && s->in_flight == 0) {
             s->cv_work.wait(lk);
         } else {
             // frames on the device: poll their completion words
             lk.unlock();
-            std::this_thread::sleep_for(std::chrono::microseconds(progress ? 5 : 20));
+            std::this_thread::sleep_for(std::chrono::microseconds(progress ? 2 : 10));
             lk.lock();
         }
     }
 }
 
-hasf_status serve_err(const char* msg)
+void free_server(hasf_server* s)
 {
-    (void)msg;
-    return HASF_EINVAL;
+    for (Lane& ln : s->lanes) {
+        if (ln.ev)
+            hipEventDestroy(ln.ev);
+        if (ln.stream)
+            hipStreamDestroy(ln.stream);
+        if (ln.d_meta)
+            hipFree(ln.d_meta);
+        if (ln.h_meta)
+            hipHostFree(ln.h_meta);
+        if (ln.h_done)
+            hipHostFree(ln.h_done);
+    }
+    if (s->pool_mem)
+        hipFree(s->pool_mem);
+    for (auto& kv : s->frames)
+        delete kv.second;
+    delete s;
 }
 
 }  // namespace
@@ -267,76 +333,59 @@ extern "C" {
 
 hasf_status hasf_serve(hasf_ctx* ctx, const hasf_serve_opts* opts, hasf_server** out)
 {
-    if (!ctx || !out)
-        return serve_err("hasf_serve: ctx and out must not be NULL");
+    if (!ctx || !out) {
+        record_error(ctx, "hasf_serve: ctx and out must not be NULL");
+        return HASF_EINVAL;
+    }
     *out = nullptr;
     hasf_serve_opts o{};
     if (opts)
         o = *opts;
-    if (o.flags != 0 || o.ring_slots < 0 || o.max_pending < 0 || o.idle_exit_ms < 0)
+    if (o.flags & HASF_SERVE_PERSISTENT) {
+        record_error(ctx, "hasf_serve: the persistent polling kernel (HASF_SERVE_PERSISTENT) is switched off");
+        return HASF_EINTERNAL;
+    }
+    if (o.flags != 0 || o.lanes < 0 || o.lanes > HASF_SERVE_LANES_MAX || o.max_batch < 0 || o.max_pending < 0) {
+        record_error(ctx, "hasf_serve: bad options");
         return HASF_EINVAL;
+    }
     hasf_server* s = new (std::nothrow) hasf_server();
     if (!s)
         return HASF_ENOMEM;
     s->ctx = ctx;
-    s->cap = o.ring_slots ? o.ring_slots : 4096;
+    s->max_batch = o.max_batch ? o.max_batch : 1024;
     s->max_pending = o.max_pending ? o.max_pending : (1 << 20);
-    const double idle_ms = o.idle_exit_ms ? o.idle_exit_ms : 2000;
-    s->idle_ticks = (unsigned long long)(idle_ms * 1e5);  // 100 MHz wall clock
     const size_t pool_bytes = (o.pool_bytes ? o.pool_bytes : ctx->hbm_budget) / 256 * 256;
     s->lds_cap = std::min(ctx->lds_per_block, (size_t)160 * 1024) - 2048;
+    s->lanes.resize(o.lanes ? o.lanes : 4);
     hipSetDevice(ctx->device);
-    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    const unsigned hflags = hipHostMallocMapped | hipHostMallocCoherent;
-    if (e == hipSuccess)
-        e = hipHostMalloc((void**)&s->ring, sizeof(ImgDesc) * s->cap, hflags);
-    if (e == hipSuccess)
-        e = hipHostMalloc((void**)&s->tail, 256, hflags);
-    if (e == hipSuccess)
-        e = hipHostMalloc((void**)&s->done, sizeof(int) * s->cap, hflags);
-    if (e == hipSuccess) {
-        s->stop = (int*)(s->tail + 8);
-        *s->tail = 0;
-        *s->stop = 0;
-        std::memset(s->done, 0, sizeof(int) * s->cap);
-        e = hipHostGetDevicePointer((void**)&s->d_ring, s->ring, 0);
+    hipError_t e = hipMalloc((void**)&s->pool_mem, std::max(pool_bytes, (size_t)256));
+    const size_t meta = 256 + sizeof(ImgDesc) * (size_t)s->max_batch;
+    for (Lane& ln : s->lanes) {
+        if (e == hipSuccess)
+            e = hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&ln.ev, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipMalloc((void**)&ln.d_meta, meta);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void**)&ln.h_meta, meta, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void**)&ln.h_done, sizeof(unsigned) * (size_t)s->max_batch,
+                              hipHostMallocMapped | hipHostMallocCoherent);
+        if (e == hipSuccess)
+            e = hipHostGetDevicePointer((void**)&ln.d_done, ln.h_done, 0);
     }
-    if (e == hipSuccess)
-        e = hipHostGetDevicePointer((void**)&s->d_tail, s->tail, 0);
-    if (e == hipSuccess)
-        e = hipHostGetDevicePointer((void**)&s->d_done, s->done, 0);
-    if (e == hipSuccess) {
-        s->d_stop = (int*)(s->d_tail + 8);
-        e = hipMalloc((void**)&s->head, 256);
-    }
-    if (e == hipSuccess)
-        e = hipMemset(s->head, 0, 256);
-    if (e == hipSuccess)
-        e = hipMalloc((void**)&s->dev_desc, sizeof(ImgDesc) * s->cap);
-    if (e == hipSuccess)
-        e = hipMalloc((void**)&s->pool_mem, pool_bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        hasf_status st = e == hipErrorOutOfMemory ? HASF_ENOMEM : HASF_EDEVICE;
-        if (s->pool_mem) hipFree(s->pool_mem);
-        if (s->dev_desc) hipFree(s->dev_desc);
-        if (s->head) hipFree(s->head);
-        if (s->done) hipHostFree(s->done);
-        if (s->tail) hipHostFree(s->tail);
-        if (s->ring) hipHostFree(s->ring);
-        if (s->stream) hipStreamDestroy(s->stream);
-        delete s;
+        char msg[256];
+        snprintf(msg, sizeof msg, "hasf_serve: %s", hipGetErrorString(e));
+        record_error(ctx, msg);
+        const hasf_status st = e == hipErrorOutOfMemory ? HASF_ENOMEM : HASF_EDEVICE;
+        free_server(s);
         return st;
     }
     s->pool.init(pool_bytes / 256);
-    s->slot_frame.assign(s->cap, nullptr);
-    // LDS for any frame that fits; two workgroups per CU
-    s->lds_launch = s->lds_cap;
-    {
-        // the largest LDS image state under the cap
-        s->lds_launch = std::min(s->lds_cap, (size_t)78 * 1024);
-    }
-    s->grid = ctx->num_cu * std::max(1, serve_occupancy(s->lds_launch));
     s->worker = std::thread(serve_loop, s);
     *out = s;
     return HASF_OK;
@@ -357,10 +406,7 @@ hasf_status hasf_serve_submit(hasf_server* s, const hasf_image* img, uint64_t* t
         return HASF_ENOMEM;
     f->img = *img;
     f->lay = image_layout(img->H, img->W, img->r, s->lds_cap);
-    if (f->lay.lds && f->lay.lds_bytes > s->lds_launch) {
-        // state fits in LDS but not in what the server kernel was launched with
-        f->lay = image_layout(img->H, img->W, img->r, 0);
-    }
+    f->cost = frame_cost(*img);
     {
         std::lock_guard<std::mutex> g(s->mu);
         if (s->stopping || s->fatal != HASF_OK) {
@@ -370,7 +416,7 @@ hasf_status hasf_serve_submit(hasf_server* s, const hasf_image* img, uint64_t* t
         if (f->lay.total() > s->pool.size * 256) {
             ++s->rejected;
             delete f;
-            return HASF_ENOMEM;  // can never be admitted
+            return HASF_ENOMEM;  // could never be admitted
         }
         if ((int)s->pending.size() >= s->max_pending) {
             delete f;
@@ -427,7 +473,7 @@ hasf_status hasf_serve_stats(hasf_server* s, hasf_stats* out)
     out->completed = s->completed;
     out->rejected = s->rejected;
     out->pending = s->pending.size();
-    out->in_flight = s->inflight.size();
+    out->in_flight = s->in_flight;
     if (!s->lat_ms.empty()) {
         std::vector<double> v = s->lat_ms;
         std::sort(v.begin(), v.end());
@@ -447,6 +493,8 @@ hasf_status hasf_serve_stats(hasf_server* s, hasf_stats* out)
     out->pool_bytes = s->pool.size * 256;
     out->pool_peak_bytes = s->pool.peak * 256;
     out->kernel_launches = s->launches;
+    out->frames_per_launch = s->launches ? (double)s->launched_frames / (double)s->launches : 0.0;
+    out->batch_max = (uint64_t)s->batch_max;
     return HASF_OK;
 }
 
@@ -461,20 +509,17 @@ hasf_status hasf_serve_stop(hasf_server* s)
     s->cv_work.notify_one();
     if (s->worker.joinable())
         s->worker.join();
-    __atomic_store_n(s->stop, 1, __ATOMIC_RELEASE);
     hipSetDevice(s->ctx->device);
-    hipError_t e = hipStreamSynchronize(s->stream);
+    hipError_t e = hipSuccess;
+    for (Lane& ln : s->lanes) {
+        const hipError_t el = hipStreamSynchronize(ln.stream);
+        if (e == hipSuccess)
+            e = el;
+    }
     const int fatal = s->fatal;
-    for (auto& kv : s->frames)
-        delete kv.second;
-    hipFree(s->pool_mem);
-    hipFree(s->dev_desc);
-    hipFree(s->head);
-    hipHostFree(s->done);
-    hipHostFree(s->tail);
-    hipHostFree(s->ring);
-    hipStreamDestroy(s->stream);
-    delete s;
+    if (fatal != HASF_OK)
+        record_error(s->ctx, s->err);
+    free_server(s);
     if (e != hipSuccess)
         return HASF_EDEVICE;
     return fatal == HASF_OK ? HASF_OK : (hasf_status)fatal;

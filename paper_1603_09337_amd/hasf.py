@@ -21,9 +21,15 @@ HASF_EAGAIN = -4
 HASF_ETIMEDOUT = -5
 HASF_EINTERNAL = -6
 HASF_R_MAX = 15
+HASF_SERVE_LANES_MAX = 16
+HASF_SERVE_PERSISTENT = 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libhasf.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+
+# torch first: the library then binds to the HIP runtime torch has already
+# loaded, so the process has one runtime (two runtimes do not share the GPU)
+import torch  # noqa: E402,F401
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -38,8 +44,8 @@ class _Image(ctypes.Structure):
 
 
 class _ServeOpts(ctypes.Structure):
-    _fields_ = [("pool_bytes", ctypes.c_size_t), ("ring_slots", ctypes.c_int), ("max_pending", ctypes.c_int),
-                ("idle_exit_ms", ctypes.c_int), ("flags", ctypes.c_uint)]
+    _fields_ = [("pool_bytes", ctypes.c_size_t), ("lanes", ctypes.c_int), ("max_batch", ctypes.c_int),
+                ("max_pending", ctypes.c_int), ("flags", ctypes.c_uint)]
 
 
 class _Result(ctypes.Structure):
@@ -52,7 +58,8 @@ class _Stats(ctypes.Structure):
                 ("pending", ctypes.c_uint64), ("in_flight", ctypes.c_uint64), ("p50_ms", ctypes.c_double),
                 ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("frames_per_s", ctypes.c_double),
                 ("mpixel_per_s", ctypes.c_double), ("pool_bytes", ctypes.c_size_t),
-                ("pool_peak_bytes", ctypes.c_size_t), ("kernel_launches", ctypes.c_uint64)]
+                ("pool_peak_bytes", ctypes.c_size_t), ("kernel_launches", ctypes.c_uint64),
+                ("frames_per_launch", ctypes.c_double), ("batch_max", ctypes.c_uint64)]
 
 
 _vp = ctypes.c_void_p
@@ -212,14 +219,15 @@ class Server:
     """Served stream on a context's device (hasf_serve). Frames are device
     tensors filtered in place; keep them alive until wait() returns."""
 
-    def __init__(self, ctx: Context, pool_bytes: int = 0, ring_slots: int = 0, max_pending: int = 0,
-                 idle_exit_ms: int = 0):
+    def __init__(self, ctx: Context, pool_bytes: int = 0, lanes: int = 0, max_batch: int = 0,
+                 max_pending: int = 0, persistent: bool = False):
         self._ctx = ctx
         h = _vp()
-        opts = _ServeOpts(pool_bytes, ring_slots, max_pending, idle_exit_ms, 0)
+        flags = HASF_SERVE_PERSISTENT if persistent else 0
+        opts = _ServeOpts(pool_bytes, lanes, max_batch, max_pending, flags)
         st = _lib.hasf_serve(ctx._h, ctypes.byref(opts), ctypes.byref(h))
         if st != HASF_OK:
-            raise HasfError(st, "hasf_serve")
+            raise HasfError(st, _lib.hasf_last_error(ctx._h).decode())
         self._h = h
         self._keep = {}
 

@@ -1,6 +1,12 @@
-"""Served stream: every frame's result is the same in the mix as alone (and as
-the oracle), also when admission is throttled by a tiny memory pool, with an
-invalid frame in the middle, and with a full queue."""
+"""Served stream through the persistent polling kernel (HASF_SERVE_PERSISTENT):
+every frame's result is the same in the mix as alone (and as the oracle), also
+when admission is throttled by a tiny memory pool, with an invalid frame in
+the middle, and with a full queue.
+
+That kernel's workgroups stopped making progress on the GPU, the cause has not
+been found, and the mode is switched off (hasf_serve returns HASF_EINTERNAL for
+it). These tests stay, skipped. The served stream in use is the launch-lane
+server, tested in test_gpu_stream.py."""
 import numpy as np
 import pytest
 
@@ -8,7 +14,9 @@ import oracle
 from gpu_util import ctx, dev, host, say
 from paper_1603_09337_amd import hasf, synth
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skip(reason="persistent polling serve kernel hung on the GPU (workgroup waves out of "
+                                      "step, cause not found); the mode is switched off")]
 
 
 def _frames(n, lo, hi, seed):
@@ -33,7 +41,7 @@ def _run(server, frames):
 
 def test_mix_equals_alone_and_oracle():
     frames = _frames(40, 30, 300, 11)
-    srv = hasf.Server(ctx(), pool_bytes=256 << 20)
+    srv = hasf.Server(ctx(), pool_bytes=256 << 20, persistent=True)
     say("serve mix 40")
     got, res = _run(srv, frames)
     st = srv.stats()
@@ -52,7 +60,7 @@ def test_mix_equals_alone_and_oracle():
 def test_tiny_pool_queues_but_completes():
     frames = _frames(12, 100, 260, 23)
     # room for one or two frames' scratch at a time (~0.5 MiB each)
-    srv = hasf.Server(ctx(), pool_bytes=1 << 20)
+    srv = hasf.Server(ctx(), pool_bytes=1 << 20, persistent=True)
     say("serve tiny pool")
     got, _ = _run(srv, frames)
     st = srv.stats()
@@ -64,7 +72,7 @@ def test_tiny_pool_queues_but_completes():
 
 def test_invalid_frame_does_not_poison_others():
     frames = _frames(6, 40, 120, 31)
-    srv = hasf.Server(ctx())
+    srv = hasf.Server(ctx(), persistent=True)
     dX = [dev(X) for X, _, _ in frames]
     t = []
     for k, (x, (_, _, r)) in enumerate(zip(dX, frames)):
@@ -84,7 +92,7 @@ def test_invalid_frame_does_not_poison_others():
 def test_full_queue_returns_eagain():
     frames = _frames(10, 200, 260, 41)
     # one or two frames' scratch fit at a time and at most one frame may wait
-    srv = hasf.Server(ctx(), pool_bytes=1 << 20, max_pending=1)
+    srv = hasf.Server(ctx(), pool_bytes=1 << 20, max_pending=1, persistent=True)
     dX = [dev(X) for X, _, _ in frames]
     accepted, saw_eagain = [], False
     for x, (_, _, r) in zip(dX, frames):

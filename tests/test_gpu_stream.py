@@ -1,0 +1,174 @@
+"""Served stream (launch-lane server, hasf_serve): every frame's result is the
+same in the mix as alone (hasf_filter on that frame) and as the oracle; also
+when admission is throttled by a tiny memory pool, with an invalid frame in the
+middle, with a full queue, and with frames of very different sizes, where a
+small frame finishes before a large one submitted with it."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import ctx, dev, host, say
+from paper_1603_09337_amd import hasf, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _frames(n, lo, hi, seed, rmax=8):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        H, W = int(rng.integers(lo, hi)), int(rng.integers(lo, hi))
+        X = synth.disks_image(H, W, np.random.default_rng(seed * 100 + k))
+        C = synth.random_binary(H, W, 0.02, seed + k) if k % 3 == 0 else None
+        out.append((X, C, int(rng.integers(0, rmax + 1))))
+    return out
+
+
+def _upload(frames):
+    dX = [dev(X) for X, _, _ in frames]
+    dC = [dev(C) if C is not None else None for _, C, _ in frames]
+    torch.cuda.synchronize()  # the server's streams do not wait for torch's
+    return dX, dC
+
+
+def _alone(X, C, r):
+    x = dev(X)
+    c = dev(C) if C is not None else None
+    ctx().filter(x, c, r)
+    ctx().sync()
+    return host(x)
+
+
+def _run(server, frames, gap_s=0.0):
+    dX, dC = _upload(frames)
+    tickets = []
+    for x, c, (_, _, r) in zip(dX, dC, frames):
+        tickets.append(server.submit(x, c, r))
+        if gap_s:
+            time.sleep(gap_s)
+    res = [server.wait(t, 60000) for t in tickets]
+    assert all(r is not None for r in res)
+    return [host(x) for x in dX], res
+
+
+def test_mix_equals_alone_and_oracle():
+    frames = _frames(40, 30, 300, 11)
+    srv = hasf.Server(ctx(), pool_bytes=256 << 20)
+    say("stream mix 40")
+    got, res = _run(srv, frames)
+    st = srv.stats()
+    srv.stop()
+    assert st["completed"] == 40 and st["p99_ms"] > 0 and st["kernel_launches"] >= 1
+    for k, ((X, C, r), g) in enumerate(zip(frames, got)):
+        assert np.array_equal(g, oracle.hasf(X, C, r)), "frame %d vs oracle" % k
+        assert np.array_equal(g, _alone(X, C, r)), "frame %d vs alone" % k
+
+
+def test_frames_arriving_during_launches_overlap():
+    # spaced arrivals: later frames go into other lanes while earlier ones run
+    frames = _frames(24, 100, 400, 17, rmax=6)
+    srv = hasf.Server(ctx(), pool_bytes=256 << 20, lanes=4)
+    say("stream spaced 24")
+    got, res = _run(srv, frames, gap_s=0.0005)
+    st = srv.stats()
+    srv.stop()
+    assert st["completed"] == 24 and st["kernel_launches"] >= 2
+    for k, ((X, C, r), g) in enumerate(zip(frames, got)):
+        assert np.array_equal(g, _alone(X, C, r)), "frame %d" % k
+    for k in range(0, 24, 6):
+        X, C, r = frames[k]
+        assert np.array_equal(got[k], oracle.hasf(X, C, r)), "frame %d vs oracle" % k
+
+
+def test_small_frames_finish_before_a_large_one():
+    big = synth.disks_image(1400, 1300, np.random.default_rng(5))
+    small = [synth.disks_image(64, 80, np.random.default_rng(6 + k)) for k in range(6)]
+    frames = [(big, None, 4)] + [(s, None, 2) for s in small]
+    srv = hasf.Server(ctx(), pool_bytes=512 << 20, lanes=2)
+    say("stream big + small")
+    dX, _ = _upload(frames)
+    tickets = [srv.submit(x, None, r) for x, (_, _, r) in zip(dX, frames)]
+    res = [srv.wait(t, 60000) for t in tickets]
+    srv.stop()
+    assert all(r is not None for r in res)
+    # the small frames share the big one's launch (each is handed out on its
+    # own completion word) or run in the other lane beside it: either way
+    # they are done first
+    assert max(r["done_s"] for r in res[1:]) < res[0]["done_s"]
+    for k, ((X, C, r), x) in enumerate(zip(frames, dX)):
+        assert np.array_equal(host(x), _alone(X, C, r)), "frame %d" % k
+    for (X, C, r), x in list(zip(frames, dX))[1:]:
+        assert np.array_equal(host(x), oracle.hasf(X, C, r))
+
+
+def test_tiny_pool_queues_but_completes():
+    frames = _frames(12, 100, 260, 23)
+    # room for one or two frames' scratch at a time (~0.5 MiB each)
+    srv = hasf.Server(ctx(), pool_bytes=1 << 20)
+    say("stream tiny pool")
+    got, _ = _run(srv, frames)
+    st = srv.stats()
+    srv.stop()
+    assert st["pool_peak_bytes"] <= 1 << 20
+    assert st["kernel_launches"] >= 2
+    for (X, C, r), g in zip(frames, got):
+        assert np.array_equal(g, oracle.hasf(X, C, r))
+
+
+def test_invalid_frame_does_not_poison_others():
+    frames = _frames(6, 40, 120, 31)
+    srv = hasf.Server(ctx())
+    dX, _ = _upload(frames)
+    t = []
+    for k, (x, (_, _, r)) in enumerate(zip(dX, frames)):
+        t.append(srv.submit(x, None, r))
+        if k == 2:
+            st = srv.submit(x, None, 99, check=False)  # r out of range
+            assert st == hasf.HASF_EINVAL
+    for tk in t:
+        assert srv.wait(tk, 60000) is not None
+    s = srv.stats()
+    srv.stop()
+    assert s["rejected"] == 1
+    for (X, _, r), x in zip(frames, dX):
+        assert np.array_equal(host(x), oracle.hasf(X, None, r))
+
+
+def test_full_queue_returns_eagain():
+    frames = _frames(10, 200, 260, 41)
+    # one or two frames' scratch fit at a time and at most one frame may wait
+    srv = hasf.Server(ctx(), pool_bytes=1 << 20, max_pending=1)
+    dX, _ = _upload(frames)
+    accepted, saw_eagain = [], False
+    for x, (_, _, r) in zip(dX, frames):
+        st = srv.submit(x, None, r, check=False)
+        if st == hasf.HASF_EAGAIN:
+            saw_eagain = True
+        else:
+            accepted.append(st)
+    for tk in accepted:
+        assert srv.wait(tk, 60000) is not None
+    srv.stop()
+    assert saw_eagain
+
+
+def test_frame_larger_than_pool_is_rejected():
+    srv = hasf.Server(ctx(), pool_bytes=64 << 10)
+    x = dev(synth.disks_image(300, 300, np.random.default_rng(1)))
+    torch.cuda.synchronize()
+    st = srv.submit(x, None, 8, check=False)
+    s = srv.stats()
+    srv.stop()
+    assert st == hasf.HASF_ENOMEM and s["rejected"] == 1
+
+
+def test_bad_options_and_switched_off_persistent_mode():
+    with pytest.raises(hasf.HasfError) as e:
+        hasf.Server(ctx(), lanes=hasf.HASF_SERVE_LANES_MAX + 1)
+    assert e.value.status == hasf.HASF_EINVAL
+    with pytest.raises(hasf.HasfError) as e:
+        hasf.Server(ctx(), persistent=True)
+    assert e.value.status == hasf.HASF_EINTERNAL
