@@ -1,5 +1,9 @@
 """Parity of the HIP path with the oracle, through the C ABI (bit-exact: all
 arithmetic is integer and the schedule is deterministic)."""
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -7,6 +11,8 @@ import oracle
 import topo_checks as tc
 from gpu_util import ctx, dev, host, say
 from paper_1603_09337_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 pytestmark = pytest.mark.gpu
 
@@ -103,6 +109,21 @@ def test_filter_large_image_global_planes():
     X, _, _ = synth.workload_disks(H=700, W=1000)
     say("filter 700x1000 r=3")
     assert np.array_equal(_filter_gpu(X, None, 3), oracle.hasf(X, None, 3))
+
+
+def test_filter_4096_r10_matches_oracle_digest():
+    # full size: the oracle's result (about four minutes on one core) is stored
+    # as a digest by tests/golden/make_large_digest.py
+    gold = json.load(open(os.path.join(GOLDEN, "hasf_4096x4096_r10.json")))
+    X, C, r = synth.workload_large()
+    assert hashlib.sha256(X.tobytes()).hexdigest() == gold["input_sha256"]
+    d = dev(X)
+    say("filter 4096x4096 r=10")
+    ctx().filter(d, None, r)
+    ctx().sync()
+    Y = host(d)
+    assert int(Y.sum()) == gold["ones"]
+    assert hashlib.sha256(np.ascontiguousarray(Y).tobytes()).hexdigest() == gold["sha256"]
 
 
 def test_batch_uneven_images():
