@@ -54,10 +54,24 @@ typedef enum {
 
 typedef struct hasf_ctx hasf_ctx;
 
+/* Defaults of hasf_opts.grid_min_pixels and hasf_opts.batch_grid_min_pixels. */
+#define HASF_GRID_MIN_PIXELS_DEFAULT ((size_t)1 << 19)
+#define HASF_BATCH_GRID_MIN_PIXELS_DEFAULT ((size_t)1 << 23)
+
+/*
+ * An image is filtered either by one workgroup (its state in LDS when it fits)
+ * or by a grid of workgroups (state in global memory, grid-wide barriers, one
+ * launch per image). The grid finishes a large image sooner but spends more
+ * device time on it, so it pays for a lone image and not in a busy batch.
+ */
 typedef struct {
-    int device;           /* HIP device ordinal */
-    size_t hbm_budget;    /* bytes the server may hold for frames; 0 = 1/4 of device memory */
-    unsigned flags;       /* reserved, must be 0 */
+    int device;             /* HIP device ordinal */
+    size_t hbm_budget;      /* bytes the server may hold for frames; 0 = 1/4 of device memory */
+    unsigned flags;         /* reserved, must be 0 */
+    size_t grid_min_pixels; /* hasf_filter (and a batch of one): images with H * W >= this use the
+                               grid. 0 = HASF_GRID_MIN_PIXELS_DEFAULT; SIZE_MAX = never */
+    size_t batch_grid_min_pixels; /* the same for batches of several images and served frames.
+                                     0 = HASF_BATCH_GRID_MIN_PIXELS_DEFAULT; SIZE_MAX = never */
 } hasf_opts;
 
 /* Create a context on opts->device (opts may be NULL: device 0, defaults).
@@ -69,7 +83,9 @@ void hasf_destroy(hasf_ctx* ctx);
  * for every later call on ctx. NULL selects the null stream. */
 hasf_status hasf_set_stream(hasf_ctx* ctx, void* hip_stream);
 
-/* Wait for ctx's stream; returns HASF_EDEVICE if queued device work failed. */
+/* Wait for ctx's stream; returns HASF_EDEVICE if queued device work failed, and
+ * HASF_EINTERNAL if a grid-filtered image since the last hasf_sync could not
+ * complete (a grid-wide barrier timed out; that image is undefined). */
 hasf_status hasf_sync(hasf_ctx* ctx);
 
 const char* hasf_strerror(int status);

@@ -17,6 +17,8 @@ hipError_t launch_edt(const uint8_t* F, int H, int W, long long ld, int frame, i
                       long long ldo, void* scratch, size_t lds_max, hipStream_t stream);
 hipError_t launch_topo(const TopoArgs& a, size_t lds_bytes, hipStream_t stream);
 int filter_occupancy(size_t lds_bytes);
+hipError_t launch_grid(const ImgDesc* d_desc, GridCtl* d_ctl, unsigned* d_err, int grid, hipStream_t stream);
+int grid_occupancy();
 }  // namespace hasf_detail
 
 using namespace hasf_detail;
@@ -197,6 +199,22 @@ hasf_status hasf_create(const hasf_opts* opts, hasf_ctx** out)
     c->d_desc = nullptr;
     c->desc_cap = 0;
     c->d_counter = nullptr;
+    c->grid_min_px = o.grid_min_pixels ? o.grid_min_pixels : HASF_GRID_MIN_PIXELS_DEFAULT;
+    c->batch_grid_min_px = o.batch_grid_min_pixels ? o.batch_grid_min_pixels : HASF_BATCH_GRID_MIN_PIXELS_DEFAULT;
+    c->d_grid_err = nullptr;
+    c->grid_pending = false;
+    c->side = nullptr;
+    c->ev_fork = c->ev_join = nullptr;
+    e = hipMalloc((void**)&c->d_grid_err, 256);
+    if (e == hipSuccess)
+        e = hipMemset(c->d_grid_err, 0, 256);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->d_grid_err)
+            hipFree(c->d_grid_err);
+        delete c;
+        return dev_fail(nullptr, e, "hasf_create");
+    }
     *out = c;
     return HASF_OK;
 }
@@ -211,6 +229,16 @@ void hasf_destroy(hasf_ctx* ctx)
         hipFree(ctx->scratch);
     if (ctx->d_desc)
         hipFree(ctx->d_desc);
+    if (ctx->d_grid_err)
+        hipFree(ctx->d_grid_err);
+    if (ctx->side) {
+        hipStreamSynchronize(ctx->side);
+        hipStreamDestroy(ctx->side);
+    }
+    if (ctx->ev_fork)
+        hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join)
+        hipEventDestroy(ctx->ev_join);
     delete ctx;
 }
 
@@ -236,6 +264,25 @@ hasf_status hasf_sync(hasf_ctx* ctx)
     e = hipGetLastError();
     if (e != hipSuccess)
         return dev_fail(ctx, e, "device");
+    if (ctx->grid_pending) {
+        // grid launches since the last check: did a barrier give up?
+        unsigned flag = 0;
+        e = hipMemcpyAsync(&flag, ctx->d_grid_err, sizeof flag, hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess)
+            return dev_fail(ctx, e, "hasf_sync: reading the grid error word");
+        ctx->grid_pending = false;
+        if (flag) {
+            e = hipMemsetAsync(ctx->d_grid_err, 0, sizeof flag, ctx->stream);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(ctx->stream);
+            if (e != hipSuccess)
+                return dev_fail(ctx, e, "hasf_sync: clearing the grid error word");
+            set_err(ctx, "hasf_sync: a grid-wide barrier of a large image timed out; its result is undefined");
+            return HASF_EINTERNAL;
+        }
+    }
     return HASF_OK;
 }
 
@@ -290,25 +337,35 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
         return HASF_OK;
     hipSetDevice(ctx->device);
 
-    // queue order: decreasing cost (pixels x levels of the whole radius loop)
-    std::vector<int> order(n);
+    // images of at least the grid threshold are filtered one at a time by a
+    // grid of workgroups; the others share one persistent launch, queued by
+    // decreasing cost (pixels x levels of the whole radius loop)
+    const size_t grid_px = n == 1 ? ctx->grid_min_px : ctx->batch_grid_min_px;
+    std::vector<int> order, big;
     std::vector<double> cost(n);
     for (int k = 0; k < n; ++k) {
-        order[k] = k;
         double lv = 0;
         for (int i = 1; i <= imgs[k].r; ++i)
             lv += levels_host(i) + 1;
         cost[k] = (double)imgs[k].H * imgs[k].W * (lv + 1);
+        if ((size_t)imgs[k].H * (size_t)imgs[k].W >= grid_px)
+            big.push_back(k);
+        else
+            order.push_back(k);
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    const int ns = (int)order.size(), nb = (int)big.size();
 
     const size_t lds_cap = std::min(ctx->lds_per_block, (size_t)160 * 1024) - 2048;
+    // meta block copied in one transfer: [queue counter | small descriptors |
+    // per big image: GridCtl, descriptor]; then the planes and level entries
+    const size_t desc_bytes = align256(256 + sizeof(ImgDesc) * (size_t)ns);
+    const size_t gmeta = align256(sizeof(GridCtl)) + 256;
+    const size_t meta_bytes = desc_bytes + gmeta * (size_t)nb;
     std::vector<ImgDesc> desc(n);
     size_t bytes = 0, lds_need = 0;
-    for (int q = 0; q < n; ++q) {
-        const hasf_image& im = imgs[order[q]];
-        const ImageLayout L = image_layout(im.H, im.W, im.r, lds_cap);
-        ImgDesc& d = desc[q];
+    auto lay_out = [&](ImgDesc& d, const hasf_image& im, size_t cap) {
+        const ImageLayout L = image_layout(im.H, im.W, im.r, cap);
         d.X = im.X;
         d.C = im.C;
         d.ld = im.ld;
@@ -316,7 +373,6 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
         d.W = im.W;
         d.r = im.r;
         d.lds = L.lds ? 1 : 0;
-        lds_need = std::max(lds_need, L.lds_bytes);
         // offsets for now; rebased after allocation
         d.gplanes = (uint64_t*)bytes;
         bytes += L.planes_bytes;
@@ -324,33 +380,85 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
         bytes += L.idx_bytes;
         d.ent_msk = (uint64_t*)bytes;
         bytes += L.msk_bytes;
-    }
-    const size_t desc_bytes = align256(256 + sizeof(ImgDesc) * (size_t)n);
-    hasf_status s = ensure_scratch(ctx, bytes + desc_bytes);
+        return L;
+    };
+    for (int q = 0; q < ns; ++q)
+        lds_need = std::max(lds_need, lay_out(desc[q], imgs[order[q]], lds_cap).lds_bytes);
+    for (int q = 0; q < nb; ++q)
+        lay_out(desc[ns + q], imgs[big[q]], 0);  // grid images keep their state in global memory
+    hasf_status s = ensure_scratch(ctx, bytes + meta_bytes);
     if (s)
         return s;
     char* base = (char*)ctx->scratch;
     for (auto& d : desc) {
-        d.gplanes = (uint64_t*)(base + desc_bytes + (size_t)d.gplanes);
-        d.ent_idx = (uint32_t*)(base + desc_bytes + (size_t)d.ent_idx);
-        d.ent_msk = (uint64_t*)(base + desc_bytes + (size_t)d.ent_msk);
+        d.gplanes = (uint64_t*)(base + meta_bytes + (size_t)d.gplanes);
+        d.ent_idx = (uint32_t*)(base + meta_bytes + (size_t)d.ent_idx);
+        d.ent_msk = (uint64_t*)(base + meta_bytes + (size_t)d.ent_msk);
     }
-    // [counter | descriptors] in one copy: the counter starts at 0
-    std::vector<char> host(desc_bytes, 0);
-    std::memcpy(host.data() + 256, desc.data(), sizeof(ImgDesc) * (size_t)n);
-    hipError_t e = hipMemcpyAsync(base, host.data(), 256 + sizeof(ImgDesc) * (size_t)n, hipMemcpyHostToDevice,
-                                  ctx->stream);
+    // the counter and every GridCtl start at 0
+    std::vector<char> host(meta_bytes, 0);
+    std::memcpy(host.data() + 256, desc.data(), sizeof(ImgDesc) * (size_t)ns);
+    for (int q = 0; q < nb; ++q)
+        std::memcpy(host.data() + desc_bytes + gmeta * q + align256(sizeof(GridCtl)), &desc[ns + q],
+                    sizeof(ImgDesc));
+    hipError_t e = hipMemcpyAsync(base, host.data(), meta_bytes, hipMemcpyHostToDevice, ctx->stream);
     if (e != hipSuccess)
         return dev_fail(ctx, e, "hipMemcpyAsync(descriptors)");
     // the pageable source must stay alive until the copy has consumed it
     e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess)
         return dev_fail(ctx, e, "hipStreamSynchronize(descriptors)");
-    const int occ = std::max(1, filter_occupancy(lds_need));
-    const int grid = std::min(n, ctx->num_cu * occ);
-    e = launch_filter((const ImgDesc*)(base + 256), n, (int*)base, grid, lds_need, ctx->stream, nullptr);
-    if (e != hipSuccess)
-        return dev_fail(ctx, e, "hasf_filter launch");
+    // Grid images: alone, on the context's stream; beside a batch, on the side
+    // stream, launched first so that their workgroups are resident while the
+    // batch's persistent workgroups take the rest of the device; the
+    // context's stream then waits for them.
+    hipStream_t gs = ctx->stream;
+    if (nb > 0 && ns > 0) {
+        // created on first use: a process has few hardware queues, and
+        // streams beyond them share one and run one after the other
+        if (!ctx->side) {
+            e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
+            if (e != hipSuccess)
+                return dev_fail(ctx, e, "hasf_filter_batch: side stream");
+        }
+        gs = ctx->side;
+        e = hipEventRecord(ctx->ev_fork, ctx->stream);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(gs, ctx->ev_fork, 0);
+        if (e != hipSuccess)
+            return dev_fail(ctx, e, "hasf_filter_batch: fork");
+    }
+    for (int q = 0; q < nb; ++q) {
+        const ImgDesc& d = desc[ns + q];
+        const int nwd = d.H * ((d.W + 63) / 64);
+        const int grid = grid_blocks(nwd, ctx->num_cu * grid_occupancy() / 2);
+        char* m = base + desc_bytes + gmeta * q;
+        e = launch_grid((const ImgDesc*)(m + align256(sizeof(GridCtl))), (GridCtl*)m, ctx->d_grid_err, grid, gs);
+        if (e != hipSuccess)
+            return dev_fail(ctx, e, "hasf_grid_kernel launch");
+        ctx->grid_pending = true;
+    }
+    if (gs != ctx->stream) {
+        e = hipEventRecord(ctx->ev_join, gs);
+        if (e != hipSuccess)
+            return dev_fail(ctx, e, "hasf_filter_batch: join");
+    }
+    if (ns > 0) {
+        const int occ = std::max(1, filter_occupancy(lds_need));
+        const int grid = std::min(ns, ctx->num_cu * occ);
+        e = launch_filter((const ImgDesc*)(base + 256), ns, (int*)base, grid, lds_need, ctx->stream, nullptr);
+        if (e != hipSuccess)
+            return dev_fail(ctx, e, "hasf_filter launch");
+    }
+    if (gs != ctx->stream) {
+        e = hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0);
+        if (e != hipSuccess)
+            return dev_fail(ctx, e, "hasf_filter_batch: join");
+    }
     return HASF_OK;
 }
 

@@ -131,6 +131,18 @@ struct ImgDesc {
     uint64_t* ent_msk;  // level entries: candidate bits
 };
 
+// Control block of one image filtered by a grid of workgroups (device memory,
+// zeroed before each launch): the grid barrier (arrival count, generation,
+// abort flag), an error word, the pass control words by barrier-epoch parity
+// and the level entry counts.
+struct GridCtl {
+    unsigned bar_count, pad0[63];
+    unsigned bar_gen, pad1[63];
+    unsigned abort, err, pad2[62];
+    int ctl[2][8];
+    unsigned cnt[HASF_LEVELS_MAX];
+};
+
 // Scratch of one image in the filter kernel: global bytes for the state (when
 // it does not fit in LDS), the saved set A and the constraint K, and the level
 // entry lists (one slot per word per level).
@@ -198,4 +210,24 @@ struct hasf_ctx {
     ImgDesc* d_desc;
     int desc_cap;
     int* d_counter;
+    // images of at least this many pixels are filtered by a grid of
+    // workgroups: alone (hasf_filter, a batch of one), in batches and served
+    size_t grid_min_px, batch_grid_min_px;
+    // sticky device word set by a grid launch whose barrier gave up; read and
+    // cleared by hasf_sync when grid work was enqueued since the last check
+    unsigned* d_grid_err;
+    bool grid_pending;
+    // grid images of a batch run on this stream, beside the batch launch
+    hipStream_t side;
+    hipEvent_t ev_fork, ev_join;
 };
+
+// Workgroups of the grid that filters one image of nwd 64-bit words: at
+// least 8 (one per XCD), about one per 4096 words, at most 16 (more
+// workgroups make every grid barrier dearer than the work they take over).
+inline int grid_blocks(int nwd, int cap)
+{
+    int g = (nwd + 4095) / 4096;
+    g = g < 8 ? 8 : (g > 16 ? 16 : g);
+    return g < cap ? g : (cap > 0 ? cap : 1);
+}

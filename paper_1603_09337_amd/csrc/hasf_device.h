@@ -114,14 +114,15 @@ __device__ __forceinline__ uint32_t expand4(uint32_t nib)
 }
 
 // Row-major 64-bit words of the nonzero bytes of X (and of C n X into K when
-// K is given): one thread per word.
+// K is given): one thread per word. Threads t0, t0 + tn, ... of the caller's
+// range (a workgroup, or every workgroup of a grid) share the words.
 template <typename PR>
 __device__ void pack_rows(const uint8_t* __restrict__ X, const uint8_t* __restrict__ C, long long ld, int H,
-                          int W, PR R, glb_u64* K)
+                          int W, PR R, glb_u64* K, int t0, int tn)
 {
     const int WW = (W + 63) >> 6, NWD = H * WW;
     const bool vec_ok = ((((uintptr_t)X) | (C ? (uintptr_t)C : 0) | (uintptr_t)ld) & 15) == 0;
-    for (int q = threadIdx.x; q < NWD; q += BLOCK) {
+    for (int q = t0; q < NWD; q += tn) {
         const int row = q / WW;
         const int w = q - row * WW;
         const int c0 = w * 64;
@@ -160,11 +161,11 @@ __device__ void pack_rows(const uint8_t* __restrict__ X, const uint8_t* __restri
 }
 
 template <typename PR>
-__device__ void unpack_rows(uint8_t* __restrict__ X, long long ld, int H, int W, PR R)
+__device__ void unpack_rows(uint8_t* __restrict__ X, long long ld, int H, int W, PR R, int t0, int tn)
 {
     const int WW = (W + 63) >> 6, NWD = H * WW;
     const bool vec_ok = ((((uintptr_t)X) | (uintptr_t)ld) & 15) == 0;
-    for (int q = threadIdx.x; q < NWD; q += BLOCK) {
+    for (int q = t0; q < NWD; q += tn) {
         const int row = q / WW;
         const int w = q - row * WW;
         const int c0 = w * 64;
@@ -192,9 +193,9 @@ __device__ void unpack_rows(uint8_t* __restrict__ X, long long ld, int H, int W,
 
 // R -> S (the four sub-images); S -> R
 template <bool LDS>
-__device__ void rows_to_sub(const Img<LDS>& g)
+__device__ void rows_to_sub(const Img<LDS>& g, int t0, int tn)
 {
-    for (int q = threadIdx.x; q < g.NWD; q += BLOCK) {
+    for (int q = t0; q < g.NWD; q += tn) {
         const int row = q / g.WW;
         const int w = q - row * g.WW;
         const uint64_t v = g.R[q];
@@ -205,9 +206,9 @@ __device__ void rows_to_sub(const Img<LDS>& g)
 }
 
 template <bool LDS>
-__device__ void sub_to_rows(const Img<LDS>& g)
+__device__ void sub_to_rows(const Img<LDS>& g, int t0, int tn)
 {
-    for (int q = threadIdx.x; q < g.NWD; q += BLOCK) {
+    for (int q = t0; q < g.NWD; q += tn) {
         const int row = q / g.WW;
         const int w = q - row * g.WW;
         const int o = (row >> 1) * g.WW + w;
@@ -217,11 +218,14 @@ __device__ void sub_to_rows(const Img<LDS>& g)
 
 // no candidate active, no word flagged (destroys R)
 template <bool LDS>
-__device__ void clear_candidates(const Img<LDS>& g)
+__device__ void clear_candidates(const Img<LDS>& g, int t0, int tn)
 {
-    for (int q = threadIdx.x; q < 4 * g.SUB; q += BLOCK) {
+    using P32 = typename Img<LDS>::P32;
+    const P32 D4 = (P32)g.D;  // 4 * SUB flag bytes, SUB a multiple of 4
+    for (int q = t0; q < 4 * g.SUB; q += tn) {
         g.M[q] = 0;
-        g.D[q] = 0;
+        if (q < g.SUB)
+            D4[q] = 0;
     }
 }
 
@@ -297,6 +301,105 @@ __device__ __forceinline__ unsigned wave_prefix(unsigned v, unsigned* total)
     return (unsigned)(__popcll(b0 & lt) + 2 * __popcll(b1 & lt) + 4 * __popcll(b2 & lt));
 }
 
+// Pointers of one subfield pass: the pass's own sub-image (si, sj) and the
+// three it reads (E/W: same rows, other column parity; N/S: other row parity,
+// same columns; diagonals: the fourth), with their re-test flags.
+template <bool LDS>
+struct PassPtrs {
+    typename Img<LDS>::P32 Ss, Ms, Sx, Sy, Sxy;
+    typename Img<LDS>::P8 Dx, Dy, Dxy;
+};
+
+template <bool LDS>
+__device__ __forceinline__ PassPtrs<LDS> pass_ptrs(const Img<LDS>& g, int si, int sj)
+{
+    const int so = 1 - si, co = 1 - sj;
+    PassPtrs<LDS> p;
+    p.Ss = g.S + g.sub(si, sj);
+    p.Ms = g.M + g.sub(si, sj);
+    p.Sx = g.S + g.sub(si, co);
+    p.Sy = g.S + g.sub(so, sj);
+    p.Sxy = g.S + g.sub(so, co);
+    p.Dx = g.D + g.sub(si, co);
+    p.Dy = g.D + g.sub(so, sj);
+    p.Dxy = g.D + g.sub(so, co);
+    return p;
+}
+
+// Tests the activated candidates of word idx (row rr of sub-image (si, sj),
+// WW words per row, H image rows) and flips the simple ones (thinning
+// deletes, thickening adds: live = M & (S ^ flip)); flags every word whose
+// test reads a changed word. Returns whether a pixel changed.
+template <bool LDS>
+__device__ __forceinline__ bool test_word(const PassPtrs<LDS>& p, int idx, int rr, int si, int sj, int WW, int H,
+                                          uint32_t flip)
+{
+    const int my_w = idx - rr * WW;
+    const bool hasL = my_w > 0, hasR = my_w + 1 < WW;
+    const uint32_t scw = p.Ss[idx];
+    const uint32_t live = p.Ms[idx] & (scw ^ flip);
+    const int row = 2 * rr + si;
+    const bool hasN = row > 0, hasS = row + 1 < H;
+    const int iN = (si ? rr : rr - 1) * WW + my_w;  // row - 1 in the other parity
+    const int iS = (si ? rr + 1 : rr) * WW + my_w;  // row + 1
+    const uint32_t xc = p.Sx[idx];
+    const uint32_t xl = hasL ? p.Sx[idx - 1] : 0u;
+    const uint32_t xr = hasR ? p.Sx[idx + 1] : 0u;
+    const uint32_t nn = hasN ? p.Sy[iN] : 0u;
+    const uint32_t sv = hasS ? p.Sy[iS] : 0u;
+    const uint32_t nc = hasN ? p.Sxy[iN] : 0u;
+    const uint32_t nl = hasN && hasL ? p.Sxy[iN - 1] : 0u;
+    const uint32_t nr = hasN && hasR ? p.Sxy[iN + 1] : 0u;
+    const uint32_t dc = hasS ? p.Sxy[iS] : 0u;
+    const uint32_t dl = hasS && hasL ? p.Sxy[iS - 1] : 0u;
+    const uint32_t dr = hasS && hasR ? p.Sxy[iS + 1] : 0u;
+    // column c of this sub-image is image column 2c + sj; its east neighbour
+    // is column c (sj = 0) or c + 1 (sj = 1) of the other column parity, its
+    // west one c - 1 or c
+    uint32_t e, w, ne, nw2, se, sw;
+    if (sj == 0) {
+        e = xc;
+        w = (xc << 1) | (xl >> 31);
+        ne = nc;
+        nw2 = (nc << 1) | (nl >> 31);
+        se = dc;
+        sw = (dc << 1) | (dl >> 31);
+    } else {
+        e = (xc >> 1) | (xr << 31);
+        w = xc;
+        ne = (nc >> 1) | (nr << 31);
+        nw2 = nc;
+        se = (dc >> 1) | (dr << 31);
+        sw = dc;
+    }
+    const uint32_t del = live & simple_bits<uint32_t>(e, ne, nn, nw2, w, sw, sv, se);
+    if (!del)
+        return false;
+    p.Ss[idx] = scw ^ del;
+    p.Dx[idx] = 1;
+    if (hasL)
+        p.Dx[idx - 1] = 1;
+    if (hasR)
+        p.Dx[idx + 1] = 1;
+    if (hasN) {
+        p.Dy[iN] = 1;
+        p.Dxy[iN] = 1;
+        if (hasL)
+            p.Dxy[iN - 1] = 1;
+        if (hasR)
+            p.Dxy[iN + 1] = 1;
+    }
+    if (hasS) {
+        p.Dy[iS] = 1;
+        p.Dxy[iS] = 1;
+        if (hasL)
+            p.Dxy[iS - 1] = 1;
+        if (hasR)
+            p.Dxy[iS + 1] = 1;
+    }
+    return true;
+}
+
 // Rounds of the four subfield passes (even,even) (even,odd) (odd,even)
 // (odd,odd) until a round changes nothing. A pass tests, on the state left by
 // the previous pass, the activated candidates of its subfield and flips the
@@ -337,12 +440,6 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
             const auto Ss = g.S + g.sub(si, sj);
             const auto Ms = g.M + g.sub(si, sj);
             const auto Ds = g.D + g.sub(si, sj);
-            const auto Sx = g.S + g.sub(si, co);   // E, W
-            const auto Sy = g.S + g.sub(so, sj);   // N, S
-            const auto Sxy = g.S + g.sub(so, co);  // diagonals
-            const auto Dx = g.D + g.sub(si, co);
-            const auto Dy = g.D + g.sub(so, sj);
-            const auto Dxy = g.D + g.sub(so, co);
             const int rows = (g.H - si + 1) >> 1;
             const int nw = rows * WW;
             lds_i32* cnt = lcnt + (sc.npass & 1);
@@ -389,6 +486,7 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
                 lcnt[(sc.npass + 1) & 1] = 0;  // every thread read it one pass ago
             const int n = *cnt;
             // test the listed words
+            const PassPtrs<LDS> pp = pass_ptrs(g, si, sj);
             bool changed_here = false;
             for (int t = threadIdx.x; t < n; t += BLOCK) {
                 const int idx = (int)g.L[t];
@@ -397,70 +495,7 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
                     --rr;
                 else if ((rr + 1) * WW <= idx)
                     ++rr;
-                const int my_w = idx - rr * WW;
-                const bool hasL = my_w > 0, hasR = my_w + 1 < WW;
-                const uint32_t scw = Ss[idx];
-                const uint32_t live = Ms[idx] & (scw ^ flip);
-                const int row = 2 * rr + si;
-                const bool hasN = row > 0, hasS = row + 1 < g.H;
-                const int iN = (si ? rr : rr - 1) * WW + my_w;  // row - 1 in the other parity
-                const int iS = (si ? rr + 1 : rr) * WW + my_w;  // row + 1
-                const uint32_t xc = Sx[idx];
-                const uint32_t xl = hasL ? Sx[idx - 1] : 0u;
-                const uint32_t xr = hasR ? Sx[idx + 1] : 0u;
-                const uint32_t nn = hasN ? Sy[iN] : 0u;
-                const uint32_t sv = hasS ? Sy[iS] : 0u;
-                const uint32_t nc = hasN ? Sxy[iN] : 0u;
-                const uint32_t nl = hasN && hasL ? Sxy[iN - 1] : 0u;
-                const uint32_t nr = hasN && hasR ? Sxy[iN + 1] : 0u;
-                const uint32_t dc = hasS ? Sxy[iS] : 0u;
-                const uint32_t dl = hasS && hasL ? Sxy[iS - 1] : 0u;
-                const uint32_t dr = hasS && hasR ? Sxy[iS + 1] : 0u;
-                // column c of this sub-image is image column 2c + sj; its east
-                // neighbour is column c (sj = 0) or c + 1 (sj = 1) of the other
-                // column parity, its west one c - 1 or c
-                uint32_t e, w, ne, nw2, se, sw;
-                if (sj == 0) {
-                    e = xc;
-                    w = (xc << 1) | (xl >> 31);
-                    ne = nc;
-                    nw2 = (nc << 1) | (nl >> 31);
-                    se = dc;
-                    sw = (dc << 1) | (dl >> 31);
-                } else {
-                    e = (xc >> 1) | (xr << 31);
-                    w = xc;
-                    ne = (nc >> 1) | (nr << 31);
-                    nw2 = nc;
-                    se = (dc >> 1) | (dr << 31);
-                    sw = dc;
-                }
-                const uint32_t del = live & simple_bits<uint32_t>(e, ne, nn, nw2, w, sw, sv, se);
-                if (del) {
-                    changed_here = true;
-                    Ss[idx] = scw ^ del;  // thin clears, thicken sets the bits of del
-                    Dx[idx] = 1;
-                    if (hasL)
-                        Dx[idx - 1] = 1;
-                    if (hasR)
-                        Dx[idx + 1] = 1;
-                    if (hasN) {
-                        Dy[iN] = 1;
-                        Dxy[iN] = 1;
-                        if (hasL)
-                            Dxy[iN - 1] = 1;
-                        if (hasR)
-                            Dxy[iN + 1] = 1;
-                    }
-                    if (hasS) {
-                        Dy[iS] = 1;
-                        Dxy[iS] = 1;
-                        if (hasL)
-                            Dxy[iS - 1] = 1;
-                        if (hasR)
-                            Dxy[iS + 1] = 1;
-                    }
-                }
+                changed_here |= test_word(pp, idx, rr, si, sj, WW, g.H, flip);
             }
             // one lane per wave records the change (a same-address store from
             // many lanes would be serialised)

@@ -65,10 +65,16 @@ __device__ __forceinline__ Img<LDS> make_img(const ImgDesc* __restrict__ dp, uin
     return g;
 }
 
+// Level entry counts: in LDS for a workgroup's image, in global memory for an
+// image shared by a grid of workgroups.
+template <bool GRID>
+using CntPtr = typename std::conditional<GRID, glb_u32*, lds_u32*>::type;
+
 // Append `acc` (candidate bits of row-major word (row, w) at level `rank`) to
-// the level's entry list, one LDS atomic per wave.
-template <bool LDS>
-__device__ __forceinline__ void flush_level(const Img<LDS>& g, lds_u32* cnt, int rank, int row, int w,
+// the level's entry list, one atomic per wave. A word has at most one entry
+// per level, so a slot never reaches NWD; the bound is checked all the same.
+template <bool LDS, bool GRID>
+__device__ __forceinline__ void flush_level(const Img<LDS>& g, CntPtr<GRID> cnt, int rank, int row, int w,
                                             uint64_t acc)
 {
     const uint64_t pred = __ballot(acc != 0);
@@ -79,30 +85,33 @@ __device__ __forceinline__ void flush_level(const Img<LDS>& g, lds_u32* cnt, int
     unsigned base = 0;
     if (lane == leader)
         base = __hip_atomic_fetch_add(cnt + rank, (unsigned)__popcll(pred), __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+                                      GRID ? __HIP_MEMORY_SCOPE_AGENT : __HIP_MEMORY_SCOPE_WORKGROUP);
     base = __shfl(base, leader);
     if (acc) {
         const unsigned slot = base + (unsigned)__popcll(pred & lanemask_lt());
-        const size_t e = (size_t)rank * g.NWD + slot;
-        g.eidx[e] = ((uint32_t)row << 10) | (uint32_t)w;
-        g.emsk[e] = acc;
+        if (slot < (unsigned)g.NWD) {
+            const size_t e = (size_t)rank * g.NWD + slot;
+            g.eidx[e] = ((uint32_t)row << 10) | (uint32_t)w;
+            g.emsk[e] = acc;
+        }
     }
 }
 
 // One distance/threshold/level stage at radius I, over all words: computes
 // the candidate bits of each level of the phase and appends them to the
-// level entry lists.
-template <int I, bool LDS>
+// level entry lists. Threads t0, t0 + tn, ... share the words (tn is a
+// multiple of the wave size).
+template <int I, bool LDS, bool GRID>
 __device__ __attribute__((noinline)) void stage(const ImgDesc* __restrict__ dp, uint64_t* smem, int mode,
-                                                lds_u32* cnt, lds_i32* ctl)
+                                                CntPtr<GRID> cnt, lds_i32* ctl, int t0, int tn)
 {
     const Img<LDS> g = make_img<LDS>(dp, smem, ctl);
     constexpr BallPairs P = make_ball_pairs(I);
     const bool frame = (mode == HC_THIN || mode == HF_THIN);
     // all lanes of a wave iterate the same number of times so that the
     // wave-level flush sees every lane
-    const int nq = (g.NWD + BLOCK - 1) / BLOCK * BLOCK;
-    for (int q = threadIdx.x; q < nq; q += BLOCK) {
+    const int nq = (g.NWD + tn - 1) / tn * tn;
+    for (int q = t0; q < nq; q += tn) {
         uint64_t base = 0;
         int row = 0, w = 0;
         if (q < g.NWD) {
@@ -168,33 +177,33 @@ __device__ __attribute__((noinline)) void stage(const ImgDesc* __restrict__ dp, 
             acc |= x & ~cov & base;
             cov |= x;
             if (k == P.n - 1 || P.v[k + 1] != P.v[k]) {
-                flush_level(g, cnt, P.rank[k], row, w, acc);
+                flush_level<LDS, GRID>(g, cnt, P.rank[k], row, w, acc);
                 acc = 0;
             }
         }
     }
 }
 
-template <bool LDS>
-__device__ __forceinline__ void run_stage(const ImgDesc* dp, uint64_t* smem, int i, int mode, lds_u32* cnt,
-                                          lds_i32* ctl)
+template <bool LDS, bool GRID>
+__device__ __forceinline__ void run_stage(const ImgDesc* dp, uint64_t* smem, int i, int mode, CntPtr<GRID> cnt,
+                                          lds_i32* ctl, int t0, int tn)
 {
     switch (i) {
-    case 1: stage<1, LDS>(dp, smem, mode, cnt, ctl); break;
-    case 2: stage<2, LDS>(dp, smem, mode, cnt, ctl); break;
-    case 3: stage<3, LDS>(dp, smem, mode, cnt, ctl); break;
-    case 4: stage<4, LDS>(dp, smem, mode, cnt, ctl); break;
-    case 5: stage<5, LDS>(dp, smem, mode, cnt, ctl); break;
-    case 6: stage<6, LDS>(dp, smem, mode, cnt, ctl); break;
-    case 7: stage<7, LDS>(dp, smem, mode, cnt, ctl); break;
-    case 8: stage<8, LDS>(dp, smem, mode, cnt, ctl); break;
-    case 9: stage<9, LDS>(dp, smem, mode, cnt, ctl); break;
-    case 10: stage<10, LDS>(dp, smem, mode, cnt, ctl); break;
-    case 11: stage<11, LDS>(dp, smem, mode, cnt, ctl); break;
-    case 12: stage<12, LDS>(dp, smem, mode, cnt, ctl); break;
-    case 13: stage<13, LDS>(dp, smem, mode, cnt, ctl); break;
-    case 14: stage<14, LDS>(dp, smem, mode, cnt, ctl); break;
-    default: stage<15, LDS>(dp, smem, mode, cnt, ctl); break;
+    case 1: stage<1, LDS, GRID>(dp, smem, mode, cnt, ctl, t0, tn); break;
+    case 2: stage<2, LDS, GRID>(dp, smem, mode, cnt, ctl, t0, tn); break;
+    case 3: stage<3, LDS, GRID>(dp, smem, mode, cnt, ctl, t0, tn); break;
+    case 4: stage<4, LDS, GRID>(dp, smem, mode, cnt, ctl, t0, tn); break;
+    case 5: stage<5, LDS, GRID>(dp, smem, mode, cnt, ctl, t0, tn); break;
+    case 6: stage<6, LDS, GRID>(dp, smem, mode, cnt, ctl, t0, tn); break;
+    case 7: stage<7, LDS, GRID>(dp, smem, mode, cnt, ctl, t0, tn); break;
+    case 8: stage<8, LDS, GRID>(dp, smem, mode, cnt, ctl, t0, tn); break;
+    case 9: stage<9, LDS, GRID>(dp, smem, mode, cnt, ctl, t0, tn); break;
+    case 10: stage<10, LDS, GRID>(dp, smem, mode, cnt, ctl, t0, tn); break;
+    case 11: stage<11, LDS, GRID>(dp, smem, mode, cnt, ctl, t0, tn); break;
+    case 12: stage<12, LDS, GRID>(dp, smem, mode, cnt, ctl, t0, tn); break;
+    case 13: stage<13, LDS, GRID>(dp, smem, mode, cnt, ctl, t0, tn); break;
+    case 14: stage<14, LDS, GRID>(dp, smem, mode, cnt, ctl, t0, tn); break;
+    default: stage<15, LDS, GRID>(dp, smem, mode, cnt, ctl, t0, tn); break;
     }
 }
 
@@ -241,11 +250,11 @@ __device__ __attribute__((noinline)) void run_image(const ImgDesc* __restrict__ 
                                                     lds_i32* ctl)
 {
     const Img<LDS> g = make_img<LDS>(dp, smem, ctl);
-    pack_rows(dp->X, dp->C, dp->ld, g.H, g.W, g.R, g.hasK ? g.K : nullptr);
+    pack_rows(dp->X, dp->C, dp->ld, g.H, g.W, g.R, g.hasK ? g.K : nullptr, threadIdx.x, BLOCK);
     for (int k = threadIdx.x; k < HASF_LEVELS_MAX; k += BLOCK)
         cnt[k] = 0;
     __syncthreads();
-    rows_to_sub(g);
+    rows_to_sub(g, threadIdx.x, BLOCK);
     __syncthreads();
     const int r = dp->r;
     for (int i = 1; i <= r; ++i) {
@@ -253,12 +262,12 @@ __device__ __attribute__((noinline)) void run_image(const ImgDesc* __restrict__ 
         // HC_i (eq. i): thin, then thicken; HF_i (eq. ii): thicken, then thin
         for (int ph = 0; ph < 4; ++ph) {
             if (i > 1 || ph > 0) {
-                sub_to_rows(g);
+                sub_to_rows(g, threadIdx.x, BLOCK);
                 __syncthreads();
             }
-            run_stage<LDS>(dp, smem, i, ph, cnt, ctl);
+            run_stage<LDS, false>(dp, smem, i, ph, cnt, ctl, threadIdx.x, BLOCK);
             __syncthreads();
-            clear_candidates(g);
+            clear_candidates(g, threadIdx.x, BLOCK);
             __syncthreads();
             level_loop<LDS>(dp, smem, ph == HC_THIN || ph == HF_THIN, nlev, cnt, ctl);
             for (int k = threadIdx.x; k < nlev; k += BLOCK)
@@ -267,13 +276,267 @@ __device__ __attribute__((noinline)) void run_image(const ImgDesc* __restrict__ 
         }
     }
     if (r > 0) {
-        sub_to_rows(g);
+        sub_to_rows(g, threadIdx.x, BLOCK);
         __syncthreads();
     }
-    unpack_rows(dp->X, dp->ld, g.H, g.W, g.R);
+    unpack_rows(dp->X, dp->ld, g.H, g.W, g.R, threadIdx.x, BLOCK);
+}
+
+// ---------------------------------------------------------------------------
+// One large image shared by a grid of workgroups. The state is in global
+// memory; every step runs over the whole grid (thread t0 of tn takes words
+// t0, t0 + tn, ...) and the workgroup barriers of the per-image kernel become
+// grid barriers. A subfield pass tests its flagged words directly (no live
+// list), so it takes one grid barrier.
+// ---------------------------------------------------------------------------
+struct GridSync {
+    GridCtl* gc;
+    unsigned nblk;
+    unsigned gen;  // grid barriers completed: the current epoch, uniform over the grid
+};
+
+// a grid barrier that waits longer than this (100 MHz ticks: 4 s) gives up
+constexpr unsigned long long GRID_WAIT_LIMIT = 400000000ull;
+
+// Pass control words (chg, prod[4]) by epoch parity: during epoch e every
+// workgroup reads copy e & 1 and writes copy (e + 1) & 1, so the decisions of
+// an epoch (skip a pass, end a round) never see a value written in the same
+// epoch by a faster workgroup. Written values are serials, larger than any
+// before them; at the start of each epoch workgroup 0 carries the read copy
+// into the written one with atomic max, so the next epoch reads the whole
+// history. The read copy of an epoch is loaded once (CtlView).
+struct CtlView {
+    int w[CTL_WORDS];
+};
+
+__device__ __forceinline__ CtlView ctl_view(const GridSync& gs)
+{
+    CtlView v;
+    const int4* p = reinterpret_cast<const int4*>(gs.gc->ctl[gs.gen & 1]);
+    const int4 a = p[0], b = p[1];
+    v.w[0] = a.x; v.w[1] = a.y; v.w[2] = a.z; v.w[3] = a.w;
+    v.w[4] = b.x; v.w[5] = b.y; v.w[6] = b.z; v.w[7] = b.w;
+    return v;
+}
+
+__device__ __forceinline__ void ctl_wr(const GridSync& gs, int x, int v)
+{
+    __hip_atomic_store(&gs.gc->ctl[(gs.gen + 1) & 1][x], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier. Every wave first waits for its own stores; one thread per
+// workgroup then releases them at device scope (L2 write-back), counts the
+// workgroup in and waits for the last arrival's generation bump, then
+// acquires (L2 invalidate). Waits are bounded: on time-out, or when another
+// workgroup has given up, it returns false and the caller returns.
+__device__ __forceinline__ bool grid_sync(GridSync& gs, int* s_ok)
+{
+    __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        GridCtl* gc = gs.gc;
+        int ok = 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned target = (gs.gen + 1) * gs.nblk;
+        const unsigned old = __hip_atomic_fetch_add(&gc->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1 == target) {
+            __hip_atomic_store(&gc->bar_gen, gs.gen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const unsigned long long t0 = wall_clock64();
+            while (__hip_atomic_load(&gc->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gs.gen) {
+                if (__hip_atomic_load(&gc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ok = 0;
+                    break;
+                }
+                if (wall_clock64() - t0 > GRID_WAIT_LIMIT) {
+                    __hip_atomic_store(&gc->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_ok = ok;
+    }
+    ++gs.gen;
+    __syncthreads();
+    // carry the history into the copy this epoch writes (see CtlView)
+    if (blockIdx.x == 0 && threadIdx.x < CTL_WORDS)
+        __hip_atomic_fetch_max(&gs.gc->ctl[(gs.gen + 1) & 1][threadIdx.x], gs.gc->ctl[gs.gen & 1][threadIdx.x],
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *s_ok != 0;
+}
+
+// Rounds of the four subfield passes until a round changes nothing (the same
+// schedule as run_rounds); each thread scans 4 flag bytes of the pass's
+// sub-image at a time and tests its flagged live words at once.
+__device__ __forceinline__ bool rounds_grid(const Img<false>& g, GridSync& gs, int* s_ok, bool thin, Sched& sc,
+                                            int t0, int tn)
+{
+    const uint32_t flip = thin ? 0u : ~0u;
+    CtlView v = ctl_view(gs);
+    for (;;) {
+        const int round_start = sc.serial;
+        for (int s = 0; s < 4; ++s) {
+            const int p = v.w[CTL_PROD + s];
+            if (p <= sc.consumed[s])
+                continue;
+            sc.consumed[s] = p;
+            const int ser = ++sc.serial;
+            const int si = s >> 1, sj = s & 1;
+            const int so = 1 - si, co = 1 - sj;
+            const PassPtrs<false> pp = pass_ptrs(g, si, sj);
+            glb_u32* D4 = (glb_u32*)(g.D + g.sub(si, sj));
+            const int nw = ((g.H - si + 1) >> 1) * g.WW;
+            bool changed = false;
+            for (int q4 = t0; 4 * q4 < nw; q4 += tn) {
+                const uint32_t f4 = D4[q4];
+                if (f4 == 0)
+                    continue;
+                D4[q4] = 0u;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int q = 4 * q4 + j;
+                    if (((f4 >> (8 * j)) & 0xFFu) && q < nw && (pp.Ms[q] & (pp.Ss[q] ^ flip)))
+                        changed |= test_word(pp, q, q / g.WW, si, sj, g.WW, g.H, flip);
+                }
+            }
+            const uint64_t chm = __ballot(changed);
+            if (chm && (int)(threadIdx.x & 63) == __ffsll((long long)chm) - 1) {
+                ctl_wr(gs, CTL_CHG, ser);
+                ctl_wr(gs, CTL_PROD + si * 2 + co, ser);
+                if (g.H > 1) {
+                    ctl_wr(gs, CTL_PROD + so * 2 + sj, ser);
+                    ctl_wr(gs, CTL_PROD + so * 2 + co, ser);
+                }
+            }
+            if (!grid_sync(gs, s_ok))
+                return false;
+            v = ctl_view(gs);
+        }
+        if (v.w[CTL_CHG] <= round_start)
+            break;
+    }
+    return true;
+}
+
+// Levels in increasing order, as level_loop; the caller has cleared the
+// candidates and the control words.
+__device__ __forceinline__ bool level_loop_grid(const Img<false>& g, GridSync& gs, int* s_ok, bool thin, int nlev,
+                                                int t0, int tn)
+{
+    Sched sc;
+    sc.serial = 0;
+    sc.npass = 0;
+    for (int k = 0; k < 4; ++k)
+        sc.consumed[k] = 0;
+    for (int k = 0; k < nlev; ++k) {
+        const unsigned c = min(__hip_atomic_load(&gs.gc->cnt[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                               (unsigned)g.NWD);
+        if (c == 0)
+            continue;
+        const int ser = ++sc.serial;
+        const size_t e0 = (size_t)k * g.NWD;
+        unsigned touched = 0;  // bit s: a word of sub-image s was activated
+        for (unsigned t = t0; t < c; t += tn) {
+            const uint32_t pe = g.eidx[e0 + t];
+            const int row = (int)(pe >> 10), w = (int)(pe & 1023u);
+            if (row >= g.H || w >= g.WW)
+                continue;
+            const uint64_t m = g.emsk[e0 + t];
+            const int o = (row >> 1) * g.WW + w;
+            const uint32_t ev = even_bits(m), od = even_bits(m >> 1);
+            if (ev) {
+                const int q = g.sub(row & 1, 0) + o;
+                __hip_atomic_fetch_or(g.M + q, ev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                g.D[q] = 1;
+                touched |= 1u << ((row & 1) * 2);
+            }
+            if (od) {
+                const int q = g.sub(row & 1, 1) + o;
+                __hip_atomic_fetch_or(g.M + q, od, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                g.D[q] = 1;
+                touched |= 1u << ((row & 1) * 2 + 1);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if (__ballot((touched >> b) & 1u) && (threadIdx.x & 63) == 0)
+                ctl_wr(gs, CTL_PROD + b, ser);
+        if (!grid_sync(gs, s_ok))
+            return false;
+        if (!rounds_grid(g, gs, s_ok, thin, sc, t0, tn))
+            return false;
+    }
+    return true;
+}
+
+// The whole filter on one image, over the grid (as run_image).
+__device__ __forceinline__ bool run_image_grid(const ImgDesc* __restrict__ dp, GridCtl* gc, int* s_ok)
+{
+    GridSync gs{gc, gridDim.x, 0u};
+    const int t0 = blockIdx.x * BLOCK + threadIdx.x, tn = gridDim.x * BLOCK;
+    const Img<false> g = make_img<false>(dp, nullptr, nullptr);
+    pack_rows(dp->X, dp->C, dp->ld, g.H, g.W, g.R, g.hasK ? g.K : nullptr, t0, tn);
+    if (!grid_sync(gs, s_ok))
+        return false;
+    rows_to_sub(g, t0, tn);
+    if (!grid_sync(gs, s_ok))
+        return false;
+    const int r = dp->r;
+    for (int i = 1; i <= r; ++i) {
+        const int nlev = levels_at(i);
+        for (int ph = 0; ph < 4; ++ph) {
+            if (i > 1 || ph > 0) {
+                sub_to_rows(g, t0, tn);
+                if (!grid_sync(gs, s_ok))
+                    return false;
+            }
+            run_stage<false, true>(dp, nullptr, i, ph, (glb_u32*)gc->cnt, nullptr, t0, tn);
+            if (!grid_sync(gs, s_ok))
+                return false;
+            clear_candidates(g, t0, tn);
+            // the threads that carried the control words at the start of this
+            // epoch clear both copies (no pass reads or writes them now)
+            if (blockIdx.x == 0 && threadIdx.x < CTL_WORDS) {
+                __hip_atomic_store(&gc->ctl[0][threadIdx.x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&gc->ctl[1][threadIdx.x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (!grid_sync(gs, s_ok))
+                return false;
+            if (!level_loop_grid(g, gs, s_ok, ph == HC_THIN || ph == HF_THIN, nlev, t0, tn))
+                return false;
+            // every workgroup has read the counts of the levels it ran (a
+            // workgroup still finishing its last round only reads zeros)
+            if (blockIdx.x == 0)
+                for (int k = threadIdx.x; k < nlev; k += BLOCK)
+                    __hip_atomic_store(&gc->cnt[k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    if (r > 0) {
+        sub_to_rows(g, t0, tn);
+        if (!grid_sync(gs, s_ok))
+            return false;
+    }
+    unpack_rows(dp->X, dp->ld, g.H, g.W, g.R, t0, tn);
+    return true;
 }
 
 }  // namespace
+
+// One image over the whole grid. If a grid barrier gave up, gc->err and the
+// caller's sticky word *err_out are set (the image is then undefined).
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void hasf_grid_kernel(
+    const ImgDesc* __restrict__ dp, GridCtl* gc, unsigned* err_out)
+{
+    __shared__ int s_ok;
+    if (!run_image_grid(dp, gc, &s_ok) && threadIdx.x == 0) {
+        __hip_atomic_store(&gc->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (err_out)
+            __hip_atomic_fetch_or(err_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
 
 // Each workgroup claims images in queue order until the queue is empty. When
 // `done` is given (host-mapped memory), done[q] becomes 1 once image q's
@@ -337,6 +600,22 @@ hipError_t launch_filter(const ImgDesc* d_desc, int n, int* d_next, int grid, si
 }  // namespace hasf_detail
 
 namespace hasf_detail {
+
+hipError_t launch_grid(const ImgDesc* d_desc, GridCtl* d_ctl, unsigned* d_err, int grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(hasf_grid_kernel, dim3(grid), dim3(BLOCK), 0, stream, d_desc, d_ctl, d_err);
+    return hipGetLastError();
+}
+
+int grid_occupancy()
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, hasf_grid_kernel, BLOCK, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return blocks;
+}
 
 int filter_occupancy(size_t lds_bytes)
 {

@@ -10,11 +10,14 @@
 // the device with the frames already there. The kernel sets a completion word
 // in host-mapped memory after each frame, so a frame is handed out, and its
 // scratch returned to the pool, as soon as it is done, not when its launch
-// ends.
+// ends. A frame of at least the context's batch_grid_min_pixels pixels is
+// launched alone, filtered by a grid of workgroups, and completes with its
+// launch.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -30,6 +33,8 @@ namespace hasf_detail {
 hipError_t launch_filter(const ImgDesc* d_desc, int n, int* d_next, int grid, size_t lds_bytes,
                          hipStream_t stream, unsigned* done);
 int filter_occupancy(size_t lds_bytes);
+hipError_t launch_grid(const ImgDesc* d_desc, GridCtl* d_ctl, unsigned* d_err, int grid, hipStream_t stream);
+int grid_occupancy();
 void record_error(hasf_ctx* ctx, const char* msg);
 }  // namespace hasf_detail
 
@@ -96,7 +101,8 @@ struct Frame {
     hasf_image img{};
     ImageLayout lay{};
     double cost = 0;
-    size_t off = 0;  // pool offset in bytes
+    bool grid = false;  // filtered by a grid of workgroups, alone in its launch
+    size_t off = 0;     // pool offset in bytes
     double t_submit = 0, t_done = 0;
     int status = HASF_OK;
     bool done = false;
@@ -106,13 +112,17 @@ struct Frame {
 struct Lane {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
-    char* d_meta = nullptr;      // device: [queue counter | descriptors]
+    char* d_meta = nullptr;      // device: [queue counter | descriptors], or [GridCtl | descriptor]
     char* h_meta = nullptr;      // pinned staging of d_meta
     unsigned* h_done = nullptr;  // host-mapped completion words, one per queue position
     unsigned* d_done = nullptr;  // the same words as the kernel addresses them
     std::vector<Frame*> frames;  // queue position -> frame (nullptr once retired)
     bool busy = false;
+    bool grid = false;           // the launch is one grid frame
 };
+
+// offset of the descriptor after a GridCtl in a lane's meta block
+constexpr size_t GRID_DESC_OFF = (sizeof(GridCtl) + 255) / 256 * 256;
 
 double frame_cost(const hasf_image& im)
 {
@@ -168,12 +178,70 @@ void retire(hasf_server* s, Frame* f, double t, int status)
     }
 }
 
+void fill_desc(hasf_server* s, const Frame* f, ImgDesc& d)
+{
+    d.X = f->img.X;
+    d.C = f->img.C;
+    d.ld = f->img.ld;
+    d.H = f->img.H;
+    d.W = f->img.W;
+    d.r = f->img.r;
+    d.lds = f->lay.lds ? 1 : 0;
+    char* base = s->pool_mem + f->off;
+    d.gplanes = (uint64_t*)base;
+    d.ent_idx = (uint32_t*)(base + f->lay.planes_bytes);
+    d.ent_msk = (uint64_t*)(base + f->lay.planes_bytes + f->lay.idx_bytes);
+}
+
+void launch_failed(hasf_server* s, hipError_t e)
+{
+    (void)hipGetLastError();
+    s->fatal = HASF_EDEVICE;
+    snprintf(s->err, sizeof s->err, "serve launch: %s", hipGetErrorString(e));
+}
+
+// A grid frame at the head of the queue: launched alone on `ln`.
+bool launch_grid_frame(hasf_server* s, Lane& ln)
+{
+    Frame* f = s->pending.front();
+    size_t off = 0;
+    if (!s->pool.alloc(f->lay.total() / 256, &off))
+        return false;
+    f->off = off * 256;
+    s->pending.pop_front();
+    std::memset(ln.h_meta, 0, GRID_DESC_OFF);  // the GridCtl starts at 0
+    fill_desc(s, f, *(ImgDesc*)(ln.h_meta + GRID_DESC_OFF));
+    ln.h_done[0] = 0;  // not written by the grid kernel; the frame completes with its launch
+    ln.frames.assign(1, f);
+    ln.busy = true;
+    ln.grid = true;
+    s->in_flight += 1;
+    ++s->launches;
+    s->launched_frames += 1;
+    s->batch_max = std::max(s->batch_max, 1);
+    const int nwd = f->img.H * ((f->img.W + 63) / 64);
+    const int grid = grid_blocks(nwd, s->ctx->num_cu * grid_occupancy() / 2);
+    hipError_t e = hipMemcpyAsync(ln.d_meta, ln.h_meta, GRID_DESC_OFF + sizeof(ImgDesc), hipMemcpyHostToDevice,
+                                  ln.stream);
+    if (e == hipSuccess)
+        e = launch_grid((const ImgDesc*)(ln.d_meta + GRID_DESC_OFF), (GridCtl*)ln.d_meta, nullptr, grid, ln.stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(ln.ev, ln.stream);
+    if (e != hipSuccess)
+        launch_failed(s, e);
+    return true;
+}
+
 // Launches the waiting frames that fit on `ln`; false if none fits now.
 bool launch_lane(hasf_server* s, Lane& ln)
 {
+    if (!s->pending.empty() && s->pending.front()->grid)
+        return launch_grid_frame(s, ln);
     std::vector<Frame*> take;
     while (!s->pending.empty() && (int)take.size() < s->max_batch) {
         Frame* f = s->pending.front();
+        if (f->grid)
+            break;  // it takes the next free lane, alone
         size_t off = 0;
         if (!s->pool.alloc(f->lay.total() / 256, &off))
             break;  // HBM footprint: wait until frames on the device finish
@@ -189,25 +257,14 @@ bool launch_lane(hasf_server* s, Lane& ln)
     ImgDesc* desc = (ImgDesc*)(ln.h_meta + 256);
     size_t lds_need = 0;
     for (int q = 0; q < n; ++q) {
-        const Frame* f = take[q];
-        ImgDesc& d = desc[q];
-        d.X = f->img.X;
-        d.C = f->img.C;
-        d.ld = f->img.ld;
-        d.H = f->img.H;
-        d.W = f->img.W;
-        d.r = f->img.r;
-        d.lds = f->lay.lds ? 1 : 0;
-        lds_need = std::max(lds_need, f->lay.lds_bytes);
-        char* base = s->pool_mem + f->off;
-        d.gplanes = (uint64_t*)base;
-        d.ent_idx = (uint32_t*)(base + f->lay.planes_bytes);
-        d.ent_msk = (uint64_t*)(base + f->lay.planes_bytes + f->lay.idx_bytes);
+        fill_desc(s, take[q], desc[q]);
+        lds_need = std::max(lds_need, take[q]->lay.lds_bytes);
         ln.h_done[q] = 0;
     }
     std::memset(ln.h_meta, 0, 256);  // the launch's queue counter starts at 0
     ln.frames = take;
     ln.busy = true;
+    ln.grid = false;
     s->in_flight += n;
     ++s->launches;
     s->launched_frames += n;
@@ -224,11 +281,8 @@ bool launch_lane(hasf_server* s, Lane& ln)
                           ln.d_done);
     if (e == hipSuccess)
         e = hipEventRecord(ln.ev, ln.stream);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        s->fatal = HASF_EDEVICE;
-        snprintf(s->err, sizeof s->err, "serve launch: %s", hipGetErrorString(e));
-    }
+    if (e != hipSuccess)
+        launch_failed(s, e);
     return true;
 }
 
@@ -243,7 +297,7 @@ void serve_loop(hasf_server* s)
             if (!ln.busy)
                 continue;
             const double t = now_s();
-            for (size_t q = 0; q < ln.frames.size(); ++q) {
+            for (size_t q = 0; q < ln.frames.size() && !ln.grid; ++q) {
                 Frame* f = ln.frames[q];
                 if (f && __atomic_load_n(ln.h_done + q, __ATOMIC_ACQUIRE)) {
                     retire(s, f, t, HASF_OK);
@@ -261,11 +315,23 @@ void serve_loop(hasf_server* s)
                     snprintf(s->err, sizeof s->err, "serve kernel: %s", hipGetErrorString(e));
                 }
             }
-            // the launch has ended: a frame without its completion word failed
+            // the launch has ended: a frame without its completion word failed;
+            // a grid frame failed if its barrier gave up
             const double t2 = now_s();
+            bool grid_ok = true;
+            if (ln.grid && e == hipSuccess) {
+                unsigned gerr = 1;
+                hipError_t ec = hipMemcpyAsync(&gerr, ln.d_meta + offsetof(GridCtl, err), sizeof gerr,
+                                               hipMemcpyDeviceToHost, ln.stream);
+                if (ec == hipSuccess)
+                    ec = hipStreamSynchronize(ln.stream);
+                grid_ok = ec == hipSuccess && gerr == 0;
+                if (ec != hipSuccess)
+                    (void)hipGetLastError();
+            }
             for (size_t q = 0; q < ln.frames.size(); ++q) {
                 if (Frame* f = ln.frames[q]) {
-                    const bool ok = e == hipSuccess && __atomic_load_n(ln.h_done + q, __ATOMIC_ACQUIRE);
+                    const bool ok = e == hipSuccess && (ln.grid ? grid_ok : __atomic_load_n(ln.h_done + q, __ATOMIC_ACQUIRE) != 0);
                     retire(s, f, t2, ok ? HASF_OK : (e == hipSuccess ? HASF_EINTERNAL : HASF_EDEVICE));
                 }
             }
@@ -360,7 +426,7 @@ hasf_status hasf_serve(hasf_ctx* ctx, const hasf_serve_opts* opts, hasf_server**
     s->lanes.resize(o.lanes ? o.lanes : 4);
     hipSetDevice(ctx->device);
     hipError_t e = hipMalloc((void**)&s->pool_mem, std::max(pool_bytes, (size_t)256));
-    const size_t meta = 256 + sizeof(ImgDesc) * (size_t)s->max_batch;
+    const size_t meta = std::max(256 + sizeof(ImgDesc) * (size_t)s->max_batch, GRID_DESC_OFF + sizeof(ImgDesc));
     for (Lane& ln : s->lanes) {
         if (e == hipSuccess)
             e = hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking);
@@ -405,7 +471,8 @@ hasf_status hasf_serve_submit(hasf_server* s, const hasf_image* img, uint64_t* t
     if (!f)
         return HASF_ENOMEM;
     f->img = *img;
-    f->lay = image_layout(img->H, img->W, img->r, s->lds_cap);
+    f->grid = (size_t)img->H * (size_t)img->W >= s->ctx->batch_grid_min_px;
+    f->lay = image_layout(img->H, img->W, img->r, f->grid ? 0 : s->lds_cap);
     f->cost = frame_cost(*img);
     {
         std::lock_guard<std::mutex> g(s->mu);

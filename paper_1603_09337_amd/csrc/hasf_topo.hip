@@ -83,9 +83,9 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     const int WW = g.WW;
 
     // X -> R, B -> Bp (row-major); R is read below until the sub-images are built
-    pack_rows(a.X, (const uint8_t*)nullptr, a.ld, a.H, a.W, g.R, (glb_u64*)nullptr);
+    pack_rows(a.X, (const uint8_t*)nullptr, a.ld, a.H, a.W, g.R, (glb_u64*)nullptr, threadIdx.x, BLOCK);
     if (a.B)
-        pack_rows(a.B, (const uint8_t*)nullptr, a.ld, a.H, a.W, Bp, (glb_u64*)nullptr);
+        pack_rows(a.B, (const uint8_t*)nullptr, a.ld, a.H, a.W, Bp, (glb_u64*)nullptr, threadIdx.x, BLOCK);
     else
         for (int q = threadIdx.x; q < g.NWD; q += BLOCK)
             Bp[q] = 0;
@@ -172,9 +172,9 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
         }
     }
     __syncthreads();
-    rows_to_sub(g);
+    rows_to_sub(g, threadIdx.x, BLOCK);
     __syncthreads();
-    clear_candidates(g);  // R is no longer needed
+    clear_candidates(g, threadIdx.x, BLOCK);  // R is no longer needed
     Sched sc;
     sched_reset(g, sc);
     __syncthreads();
@@ -192,9 +192,9 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
         run_rounds(g, a.thin != 0, sc);
     }
     __syncthreads();
-    sub_to_rows(g);
+    sub_to_rows(g, threadIdx.x, BLOCK);
     __syncthreads();
-    unpack_rows(a.X, a.ld, a.H, a.W, g.R);
+    unpack_rows(a.X, a.ld, a.H, a.W, g.R, threadIdx.x, BLOCK);
 }
 
 }  // namespace

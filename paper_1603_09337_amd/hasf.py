@@ -35,7 +35,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 
 class _Opts(ctypes.Structure):
-    _fields_ = [("device", ctypes.c_int), ("hbm_budget", ctypes.c_size_t), ("flags", ctypes.c_uint)]
+    _fields_ = [("device", ctypes.c_int), ("hbm_budget", ctypes.c_size_t), ("flags", ctypes.c_uint),
+                ("grid_min_pixels", ctypes.c_size_t), ("batch_grid_min_pixels", ctypes.c_size_t)]
 
 
 class _Image(ctypes.Structure):
@@ -121,12 +122,13 @@ def _img(t, name):
 
 
 class Context:
-    def __init__(self, device: int = 0, hbm_budget: int = 0):
+    def __init__(self, device: int = 0, hbm_budget: int = 0, grid_min_pixels: int = 0,
+                 batch_grid_min_pixels: int = 0):
         import torch
         self._torch = torch
         self.device = device
         h = _vp()
-        opts = _Opts(device, hbm_budget, 0)
+        opts = _Opts(device, hbm_budget, 0, grid_min_pixels, batch_grid_min_pixels)
         st = _lib.hasf_create(ctypes.byref(opts), ctypes.byref(h))
         if st != HASF_OK:
             raise HasfError(st, _lib.hasf_last_error(None).decode())

@@ -84,23 +84,33 @@ def test_frames_arriving_during_launches_overlap():
 
 
 def test_small_frames_finish_before_a_large_one():
+    # one lane, no grid path: a blocker keeps the lane busy while the large and
+    # the small frames are submitted, so all of them share the next launch;
+    # each small frame is handed out on its own completion word, before the
+    # large one's workgroup is done
+    c = hasf.Context(0, grid_min_pixels=2**64 - 1, batch_grid_min_pixels=2**64 - 1)
+    blocker = synth.disks_image(700, 700, np.random.default_rng(4))
     big = synth.disks_image(1400, 1300, np.random.default_rng(5))
     small = [synth.disks_image(64, 80, np.random.default_rng(6 + k)) for k in range(6)]
-    frames = [(big, None, 4)] + [(s, None, 2) for s in small]
-    srv = hasf.Server(ctx(), pool_bytes=512 << 20, lanes=2)
-    say("stream big + small")
+    frames = [(blocker, None, 6), (big, None, 4)] + [(s, None, 2) for s in small]
+    srv = hasf.Server(c, pool_bytes=512 << 20, lanes=1)
+    say("stream blocker, big + small")
     dX, _ = _upload(frames)
-    tickets = [srv.submit(x, None, r) for x, (_, _, r) in zip(dX, frames)]
+    tickets = [srv.submit(dX[0], None, frames[0][2])]
+    t0 = time.time()
+    while srv.stats()["in_flight"] == 0:  # the blocker's launch holds the lane
+        assert time.time() - t0 < 10
+        time.sleep(0.0002)
+    tickets += [srv.submit(x, None, r) for x, (_, _, r) in zip(dX[1:], frames[1:])]
     res = [srv.wait(t, 60000) for t in tickets]
+    st = srv.stats()
     srv.stop()
     assert all(r is not None for r in res)
-    # the small frames share the big one's launch (each is handed out on its
-    # own completion word) or run in the other lane beside it: either way
-    # they are done first
-    assert max(r["done_s"] for r in res[1:]) < res[0]["done_s"]
+    assert st["kernel_launches"] == 2
+    assert max(r["done_s"] for r in res[2:]) < res[1]["done_s"]
     for k, ((X, C, r), x) in enumerate(zip(frames, dX)):
         assert np.array_equal(host(x), _alone(X, C, r)), "frame %d" % k
-    for (X, C, r), x in list(zip(frames, dX))[1:]:
+    for (X, C, r), x in list(zip(frames, dX))[2:]:
         assert np.array_equal(host(x), oracle.hasf(X, C, r))
 
 
@@ -172,3 +182,17 @@ def test_bad_options_and_switched_off_persistent_mode():
     with pytest.raises(hasf.HasfError) as e:
         hasf.Server(ctx(), persistent=True)
     assert e.value.status == hasf.HASF_EINTERNAL
+
+
+def test_grid_frames_in_the_stream():
+    # frames of at least 40000 pixels are launched alone on the grid path
+    c = hasf.Context(0, batch_grid_min_pixels=40000)
+    frames = _frames(16, 60, 380, 53, rmax=6)
+    srv = hasf.Server(c, pool_bytes=256 << 20, lanes=3)
+    say("stream with grid frames:", sum(X.size >= 40000 for X, _, _ in frames))
+    got, _ = _run(srv, frames, gap_s=0.0003)
+    st = srv.stats()
+    srv.stop()
+    assert st["completed"] == 16
+    for k, ((X, C, r), g) in enumerate(zip(frames, got)):
+        assert np.array_equal(g, oracle.hasf(X, C, r)), "frame %d" % k
