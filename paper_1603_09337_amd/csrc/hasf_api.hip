@@ -14,7 +14,7 @@ hipError_t launch_filter(const ImgDesc* d_desc, int n, int* d_next, int grid, si
 int filter_block();
 size_t edt_scratch_bytes(int H, int W);
 hipError_t launch_edt(const uint8_t* F, int H, int W, long long ld, int frame, int invert, uint32_t* d2,
-                      long long ldo, void* scratch, size_t lds_max, hipStream_t stream);
+                      long long ldo, void* scratch, size_t lds_max, int nxcd, hipStream_t stream);
 hipError_t launch_topo(const TopoArgs& a, size_t lds_bytes, hipStream_t stream);
 int filter_occupancy(size_t lds_bytes);
 hipError_t launch_grid(const ImgDesc* d_desc, GridCtl* d_ctl, unsigned* d_err, int grid, hipStream_t stream);
@@ -191,6 +191,12 @@ hasf_status hasf_create(const hasf_opts* opts, hasf_ctx** out)
     c->device = o.device;
     c->stream = nullptr;
     c->num_cu = prop.multiProcessorCount;
+    c->num_xcd = 1;
+    if (hipDeviceGetAttribute(&c->num_xcd, hipDeviceAttributeNumberOfXccs, o.device) != hipSuccess ||
+        c->num_xcd < 1) {
+        (void)hipGetLastError();
+        c->num_xcd = 1;
+    }
     c->lds_per_block = prop.sharedMemPerBlock;
     c->hbm_budget = o.hbm_budget ? o.hbm_budget : prop.totalGlobalMem / 4;
     c->err[0] = 0;
@@ -301,7 +307,7 @@ hasf_status hasf_edt_sq(hasf_ctx* ctx, const uint8_t* feat, int H, int W, int64_
         return s;
     const size_t lds_max = std::min(ctx->lds_per_block, (size_t)160 * 1024);
     hipError_t e = launch_edt(feat, H, W, ld, border_is_feature ? 1 : 0, 0, d2, ld_out, ctx->scratch, lds_max,
-                              ctx->stream);
+                              ctx->num_xcd, ctx->stream);
     if (e != hipSuccess)
         return dev_fail(ctx, e, "hasf_edt_sq launch");
     return HASF_OK;
@@ -529,7 +535,7 @@ hasf_status run_topo(hasf_ctx* ctx, uint8_t* X, const uint8_t* B, int H, int W, 
     const size_t lds_max = std::min(ctx->lds_per_block, (size_t)160 * 1024);
     // thinning: distance to the background (zero bytes of X) and the outside
     hipError_t e = launch_edt(X, H, W, ld, thin ? 1 : 0, thin ? 1 : 0, (uint32_t*)(base + oP), W, base + oE,
-                              lds_max, ctx->stream);
+                              lds_max, ctx->num_xcd, ctx->stream);
     if (e != hipSuccess)
         return dev_fail(ctx, e, "edt launch");
     TopoArgs a;

@@ -202,6 +202,7 @@ struct hasf_ctx {
     hipStream_t stream;
     size_t hbm_budget;
     int num_cu;
+    int num_xcd;  // XCDs (accelerator complex dies); workgroups are dealt to them round-robin
     size_t lds_per_block;
     char err[512];
     // growable device scratch

@@ -6,59 +6,94 @@
 // columns and whole rows to threads; a column scan is sequential in rows, so
 // here phase 1 is split into 32-row segments that are independent:
 //
-//   edt_colmask   one thread per (column, 32-row segment): the segment's
-//                 features as a 32-bit mask (reads the input once).
-//   edt_colcarry  one thread per column: for every segment, the nearest
+//   edt_colmask   one thread per 4 columns and 32-row segment: the segment's
+//                 features as 32-bit masks (reads the input once, 4 bytes per
+//                 load).
+//   edt_colcarry  16 threads per column: for every segment, the nearest
 //                 feature row above the segment and below it (a prefix-max /
-//                 suffix-min over the segment masks).
-//   edt_rows      one workgroup per strip of rows: g of the strip from the
+//                 suffix-min over the segment masks, in 16 chunks combined
+//                 through LDS).
+//   edt_rows32    one workgroup per strip of rows: g^2 of the strip from the
 //                 masks and carries (O(1) per pixel with clz/ctz), kept in
-//                 LDS, then phase 2 per pixel as an exact windowed minimum:
+//                 LDS as uint32 with "infinity" columns padding each row,
+//                 then phase 2 per pixel as an exact windowed minimum:
 //                 starting from g(i, j)^2, columns j -+ 1, j -+ 2, ... are
 //                 visited until d^2 reaches the best value found, beyond which
-//                 no column can improve it. The result is written once.
+//                 no column can improve it. Within the padding a candidate
+//                 costs one saturating add and one min; the result is
+//                 written once. edt_rows is the same with uint16 g, for rows
+//                 too wide for a uint32 strip in LDS.
 //
 // HBM traffic: 1 B/px read + 4 B/px written, plus 3/8 B/px of masks and
 // carries; the per-column g never leaves LDS. With no feature at all (and no
 // frame) every column is empty, which the strip kernel sees by itself.
+#include <algorithm>
+#include <atomic>
+
 #include "hasf_common.h"
 
 namespace {
 
 constexpr int SEG = 32;
 constexpr uint16_t G_INF = 0xFFFF;
+constexpr uint32_t G2_INF = 0xFFFFFFFFu;
 constexpr int ROWS_BLOCK = 1024;
+constexpr int PAD = 16;  // "infinity" columns on each side of a uint32 strip row
 constexpr int NO_ROW_BELOW = 0x7FFFFFFF;
+constexpr int CARRY_GROUPS = 16;  // threads per column in edt_colcarry
+constexpr int CARRY_COLS = 16;    // columns per edt_colcarry workgroup
 
-// one thread per (column, 32-row segment): the segment's features as a mask
+// one thread per 4 columns and 32-row segment: the segment's features as masks
 __global__ __launch_bounds__(256) void edt_colmask(const uint8_t* __restrict__ F, long long ld, int H, int W,
-                                                   int invert, uint32_t* __restrict__ mask)
+                                                   int invert, int vec4, uint32_t* __restrict__ mask)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c4 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
     const int s = blockIdx.y;
-    if (c >= W)
+    if (c4 >= W)
         return;
     const int r0 = s * SEG;
     const int n = min(SEG, H - r0);
-    const uint8_t* p = F + (long long)r0 * ld + c;
-    uint32_t m = 0;
+    const uint32_t valid = n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u);
+    const uint32_t flip = invert ? valid : 0u;
+    const uint8_t* p = F + (long long)r0 * ld + c4;
+    if (vec4 && c4 + 4 <= W) {
+        uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
 #pragma unroll 8
-    for (int b = 0; b < n; ++b)
-        m |= (uint32_t)((p[(long long)b * ld] != 0) != (invert != 0)) << b;
-    mask[(size_t)s * W + c] = m;
+        for (int b = 0; b < n; ++b) {
+            const uint32_t v = *reinterpret_cast<const uint32_t*>(p + (long long)b * ld);
+            m0 |= (uint32_t)((v & 0xFFu) != 0) << b;
+            m1 |= (uint32_t)((v & 0xFF00u) != 0) << b;
+            m2 |= (uint32_t)((v & 0xFF0000u) != 0) << b;
+            m3 |= (uint32_t)((v & 0xFF000000u) != 0) << b;
+        }
+        uint32_t* out = mask + (size_t)s * W + c4;
+        out[0] = m0 ^ flip;
+        out[1] = m1 ^ flip;
+        out[2] = m2 ^ flip;
+        out[3] = m3 ^ flip;
+        return;
+    }
+    for (int c = c4; c < min(c4 + 4, W); ++c) {
+        uint32_t m = 0;
+        for (int b = 0; b < n; ++b)
+            m |= (uint32_t)(p[(long long)b * ld + (c - c4)] != 0) << b;
+        mask[(size_t)s * W + c] = m ^ flip;
+    }
 }
 
 // Per column and segment: the nearest feature row above the segment
 // (above, -1 if none) and below it (below, NO_ROW_BELOW if none). A block
-// covers 64 columns; the 4 threads of a column split its segments into 4
-// consecutive groups, scan them, and combine through LDS.
-__global__ __launch_bounds__(256) void edt_colcarry(const uint32_t* __restrict__ mask, int nseg, int W,
-                                                    int* __restrict__ above, int* __restrict__ below)
+// covers CARRY_COLS columns; the CARRY_GROUPS threads of a column split its
+// segments into consecutive groups, scan them, and combine through LDS.
+__global__ __launch_bounds__(CARRY_COLS* CARRY_GROUPS) void edt_colcarry(const uint32_t* __restrict__ mask,
+                                                                         int nseg, int W,
+                                                                         int* __restrict__ above,
+                                                                         int* __restrict__ below)
 {
-    __shared__ int glast[4][64], gfirst[4][64];
-    const int lc = threadIdx.x & 63, grp = threadIdx.x >> 6;
-    const int c = blockIdx.x * 64 + lc;
-    const int G = (nseg + 3) >> 2;
+    __shared__ int glast[CARRY_GROUPS][CARRY_COLS], gfirst[CARRY_GROUPS][CARRY_COLS];
+    const int lc = threadIdx.x % CARRY_COLS, grp = threadIdx.x / CARRY_COLS;
+    const int c = blockIdx.x * CARRY_COLS + lc;
+    const int G = (nseg + CARRY_GROUPS - 1) / CARRY_GROUPS;
     const int s0 = grp * G, s1 = min(nseg, s0 + G);
     int last = -1, first = NO_ROW_BELOW;
     if (c < W) {
@@ -80,7 +115,7 @@ __global__ __launch_bounds__(256) void edt_colcarry(const uint32_t* __restrict__
     int up = -1, dn = NO_ROW_BELOW;
     for (int k = 0; k < grp; ++k)
         up = max(up, glast[k][lc]);
-    for (int k = 3; k > grp; --k)
+    for (int k = CARRY_GROUPS - 1; k > grp; --k)
         dn = min(dn, gfirst[k][lc]);
 #pragma unroll 8
     for (int s = s0; s < s1; ++s) {
@@ -179,6 +214,122 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows(const uint32_t* __restric
     }
 }
 
+// edt_rows with g^2 as uint32 in LDS: each strip row holds PAD columns, the
+// W values, PAD columns. Without the frame the padding is G2_INF (it cannot
+// improve best); with the frame every column outside the window is a feature
+// column, g^2 = 0, so the search finds the horizontal distance to the frame
+// by itself. A search within PAD columns needs no bounds checks; a saturating
+// add keeps g^2 = G2_INF out of the minimum.
+//
+// Workgroups are dealt to the XCDs round-robin; block b takes strip
+// (b % nxcd) * per + b / nxcd, so each XCD takes a contiguous run of strips
+// and the strips of one segment read its masks and carries through one L2.
+template <int STRIP>
+__global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restrict__ mask,
+                                                         const int* __restrict__ above,
+                                                         const int* __restrict__ below, int H, int W, int frame,
+                                                         int nxcd, int per, uint32_t* __restrict__ d2,
+                                                         long long ldo)
+{
+    extern __shared__ uint32_t g2s[];
+    const int WP = W + 2 * PAD;
+    const int strip_id = (int)(blockIdx.x % nxcd) * per + (int)(blockIdx.x / nxcd);
+    const int r0 = strip_id * STRIP;
+    if (r0 >= H)
+        return;
+    const int nr = min(STRIP, H - r0);
+    const int s = r0 / SEG;
+    const uint32_t pad = frame ? 0u : G2_INF;
+    for (int t = threadIdx.x; t < nr * 2 * PAD; t += blockDim.x) {
+        const int r = t / (2 * PAD), k = t - r * (2 * PAD);
+        g2s[r * WP + (k < PAD ? k : W + k)] = pad;
+    }
+    int has = 0;
+#pragma unroll 4
+    for (int c = threadIdx.x; c < W; c += blockDim.x) {
+        const uint32_t m = mask[(size_t)s * W + c];
+        const int up0 = above[(size_t)s * W + c];
+        const int dn0 = below[(size_t)s * W + c];
+        has |= (m != 0) | (up0 >= 0) | (dn0 != NO_ROW_BELOW);
+        // nearest feature row above the strip (at or before r0 - 1) and below
+        // it (at or after r0 + nr), then running values down and up the strip;
+        // "none" is far enough away (2^20 rows) that it never wins a minimum
+        // against a real one and is recognised below
+        const int b0 = r0 - s * SEG;
+        const uint32_t before = b0 ? m & (0xFFFFFFFFu >> (32 - b0)) : 0u;
+        const uint32_t after = (b0 + nr < 32) ? m >> (b0 + nr) : 0u;
+        constexpr int FAR = 1 << 20;
+        int up = before ? s * SEG + 31 - __clz(before) : (up0 >= 0 ? up0 : -FAR);
+        int dn = after ? r0 + nr + __ffs(after) - 1 : (dn0 != NO_ROW_BELOW ? dn0 : H + FAR);
+        int ups[STRIP];
+#pragma unroll
+        for (int r = 0; r < STRIP; ++r) {
+            if (r < nr && ((m >> (b0 + r)) & 1u))
+                up = r0 + r;
+            ups[r] = up;
+        }
+#pragma unroll
+        for (int r = STRIP - 1; r >= 0; --r) {
+            if (r >= nr)
+                continue;
+            const int i = r0 + r;
+            if ((m >> (b0 + r)) & 1u)
+                dn = i;
+            int g = min(i - ups[r], dn - i);
+            if (frame)
+                g = min(g, min(i + 1, H - i));
+            g2s[r * WP + PAD + c] = g >= FAR ? G2_INF : (uint32_t)g * (uint32_t)g;
+        }
+    }
+    const int any = __syncthreads_or(has);
+    if (!frame && !any) {
+        for (int r = 0; r < nr; ++r)
+            for (int j = threadIdx.x; j < W; j += blockDim.x)
+                d2[(long long)(r0 + r) * ldo + j] = G2_INF;
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < STRIP; ++r) {
+        if (r >= nr)
+            break;
+        const uint32_t* gr = g2s + r * WP + PAD;
+        uint32_t* out = d2 + (long long)(r0 + r) * ldo;
+        for (int j = threadIdx.x; j < W; j += blockDim.x) {
+            uint32_t best = gr[j];
+            // d = 1 .. PAD, four per step, no bounds checks (with the frame,
+            // the zero padding supplies the distance to the left and right
+            // frame when it is within PAD columns)
+            int d = 1;
+#pragma unroll
+            for (int step = 0; step < PAD / 4; ++step) {
+                const int d0 = 1 + 4 * step;
+                if ((uint32_t)(d0 * d0) >= best)
+                    break;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t dd = (uint32_t)((d0 + u) * (d0 + u));
+                    best = min(best, __builtin_elementwise_add_sat(dd, gr[j - d0 - u]));
+                    best = min(best, __builtin_elementwise_add_sat(dd, gr[j + d0 + u]));
+                }
+                d = d0 + 4;
+            }
+            // beyond the padding: checked, one column per side at a time
+            if (frame && (uint32_t)d * (uint32_t)d < best) {
+                const uint32_t e = (uint32_t)min(j + 1, W - j);
+                best = min(best, e * e);
+            }
+            for (; (uint32_t)d * (uint32_t)d < best && (j - d >= 0 || j + d < W); ++d) {
+                const uint32_t dd = (uint32_t)d * (uint32_t)d;
+                if (j - d >= 0)
+                    best = min(best, __builtin_elementwise_add_sat(dd, gr[j - d]));
+                if (j + d < W)
+                    best = min(best, __builtin_elementwise_add_sat(dd, gr[j + d]));
+            }
+            out[j] = best;
+        }
+    }
+}
+
 }  // namespace
 
 namespace hasf_detail {
@@ -192,8 +343,9 @@ size_t edt_scratch_bytes(int H, int W)
 // scratch: device memory of edt_scratch_bytes(H, W)
 // invert != 0: the features are the zero bytes of F instead of the nonzero ones
 hipError_t launch_edt(const uint8_t* F, int H, int W, long long ld, int frame, int invert, uint32_t* d2,
-                      long long ldo, void* scratch, size_t lds_max, hipStream_t stream)
+                      long long ldo, void* scratch, size_t lds_max, int nxcd, hipStream_t stream)
 {
+    nxcd = std::max(1, nxcd);
     const int nseg = (H + SEG - 1) / SEG;
     char* p = (char*)scratch;
     uint32_t* mask = (uint32_t*)p;
@@ -202,25 +354,61 @@ hipError_t launch_edt(const uint8_t* F, int H, int W, long long ld, int frame, i
     p += ((size_t)nseg * W * sizeof(int) + 255) / 256 * 256;
     int* below = (int*)p;
 
-    hipLaunchKernelGGL(edt_colmask, dim3((W + 255) / 256, nseg), dim3(256), 0, stream, F, ld, H, W, invert, mask);
-    hipLaunchKernelGGL(edt_colcarry, dim3((W + 63) / 64), dim3(256), 0, stream, mask, nseg, W, above, below);
-    // strip height: a divisor of 32, at most 8 rows, as LDS allows (1 KiB is
-    // left for the kernel's static LDS)
+    const int vec4 = ((((uintptr_t)F) | (uintptr_t)ld) & 3) == 0;
+    hipLaunchKernelGGL(edt_colmask, dim3((W + 1023) / 1024, nseg), dim3(256), 0, stream, F, ld, H, W, invert, vec4,
+                       mask);
+    hipLaunchKernelGGL(edt_colcarry, dim3((W + CARRY_COLS - 1) / CARRY_COLS), dim3(CARRY_COLS * CARRY_GROUPS), 0,
+                       stream, mask, nseg, W, above, below);
+    // strip height: a divisor of 32 (a strip lies in one segment), as LDS
+    // allows (1 KiB is left for the kernels' static LDS): up to 4 rows of
+    // padded uint32 g^2 in half the LDS (two workgroups per CU), else in all
+    // of it, else up to 8 rows of uint16 g
     const size_t lds_dyn = lds_max - 1024;
+    const int block = std::min(512, std::max(256, (W + 63) / 64 * 64));
+    static std::atomic<bool> attr{false};
+    if (!attr.load(std::memory_order_acquire)) {
+        hipError_t e = hipFuncSetAttribute((const void*)edt_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_dyn);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)edt_rows32<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds_dyn);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)edt_rows32<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds_dyn);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)edt_rows32<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds_dyn);
+        if (e != hipSuccess)
+            return e;
+        attr.store(true, std::memory_order_release);
+    }
+    const size_t row32 = (size_t)(W + 2 * PAD) * 4;
+    if (row32 <= lds_dyn) {
+        // two rows per strip and 512 threads: four workgroups share a CU, so
+        // one's global loads overlap the others' searches (measured best at
+        // 4096^2 among 1, 2, 4 rows and 256 to 1024 threads)
+        int strip = 2;
+        while (strip > 1 && strip * row32 > lds_dyn / 4)
+            strip >>= 1;
+        const int nstrips = (H + strip - 1) / strip;
+        const int per = (nstrips + nxcd - 1) / nxcd;
+        const dim3 grid(per * nxcd);
+        if (strip == 4)
+            hipLaunchKernelGGL(edt_rows32<4>, grid, dim3(block), 4 * row32, stream, mask, above, below, H, W, frame,
+                               nxcd, per, d2, ldo);
+        else if (strip == 2)
+            hipLaunchKernelGGL(edt_rows32<2>, grid, dim3(block), 2 * row32, stream, mask, above, below, H, W, frame,
+                               nxcd, per, d2, ldo);
+        else
+            hipLaunchKernelGGL(edt_rows32<1>, grid, dim3(block), row32, stream, mask, above, below, H, W, frame,
+                               nxcd, per, d2, ldo);
+        return hipGetLastError();
+    }
     int strip = 8;
     while (strip > 1 && (size_t)strip * W * 2 > lds_dyn)
         strip >>= 1;
-    const size_t lds = (size_t)strip * W * 2;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)edt_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds_dyn);
-        if (e != hipSuccess)
-            return e;
-        attr = true;
-    }
-    hipLaunchKernelGGL(edt_rows, dim3((H + strip - 1) / strip), dim3(ROWS_BLOCK), lds, stream, mask, above,
-                       below, H, W, frame, strip, d2, ldo);
+    hipLaunchKernelGGL(edt_rows, dim3((H + strip - 1) / strip), dim3(block), (size_t)strip * W * 2, stream, mask,
+                       above, below, H, W, frame, strip, d2, ldo);
     return hipGetLastError();
 }
 
