@@ -198,3 +198,48 @@ def test_thicken_empty_set_adds_nothing():
     ctx().homotopic_thicken(Yd, dev(V))
     ctx().sync()
     assert not host(Yd).any()
+
+
+# H + W at the limit (65535): the widest rows take the uint16 row pass of the
+# EDT and 1024-word rows in the filter; the tallest columns take 2048 segments
+EXTREME_SHAPES = [(1, 65534), (65534, 1), (3, 65532), (65532, 3)]
+
+
+@pytest.mark.parametrize("shape", EXTREME_SHAPES)
+def test_edt_extreme_shapes(shape):
+    for k, d in enumerate((0.0, 0.0005, 0.3)):
+        F = synth.random_binary(shape[0], shape[1], d, 71 + k)
+        say("edt extreme", shape, d)
+        for frame in (False, True):
+            assert np.array_equal(_edt_gpu(F, frame), oracle.edt_sq(F, frame)), (shape, d, frame)
+
+
+@pytest.mark.parametrize("shape", EXTREME_SHAPES)
+def test_filter_extreme_shapes(shape):
+    X = synth.random_binary(shape[0], shape[1], 0.55, 81)
+    C = synth.random_binary(shape[0], shape[1], 0.02, 82)
+    say("filter extreme", shape)
+    assert np.array_equal(_filter_gpu(X, C, 3), oracle.hasf(X, C, 3))
+
+
+def test_thicken_from_one_pixel_over_a_long_row():
+    # priorities up to 15999^2: the distinct-value ranking spans a 256 M range
+    Y = np.zeros((1, 16000), np.uint8)
+    Y[0, 0] = 1
+    V = np.ones((1, 16000), np.uint8)
+    Yd = dev(Y)
+    say("thicken 1x16000 from one pixel")
+    ctx().homotopic_thicken(Yd, dev(V))
+    ctx().sync()
+    assert np.array_equal(host(Yd), oracle.homotopic_thicken(Y, V))
+
+
+def test_grid_extreme_shapes():
+    from test_gpu_grid import grid_ctx
+    for shape in [(3, 65532), (65532, 3)]:
+        X = synth.random_binary(shape[0], shape[1], 0.55, 91)
+        d = dev(X)
+        say("grid extreme", shape)
+        grid_ctx().filter(d, None, 3)
+        grid_ctx().sync()
+        assert np.array_equal(host(d), oracle.hasf(X, None, 3)), shape
