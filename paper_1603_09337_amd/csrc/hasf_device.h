@@ -326,78 +326,106 @@ __device__ __forceinline__ PassPtrs<LDS> pass_ptrs(const Img<LDS>& g, int si, in
     return p;
 }
 
-// Tests the activated candidates of word idx (row rr of sub-image (si, sj),
-// WW words per row, H image rows) and flips the simple ones (thinning
-// deletes, thickening adds: live = M & (S ^ flip)); flags every word whose
-// test reads a changed word. Returns whether a pixel changed.
+// The words a subfield-pass test of word idx reads (row rr of sub-image
+// (si, sj), WW words per row, H image rows): its own S and M words and the
+// neighbouring words of the other three sub-images.
+struct WordNbhd {
+    int idx, iN, iS;
+    bool hasL, hasR, hasN, hasS;
+    uint32_t scw, m, xc, xl, xr, nn, sv, nc, nl, nr, dc, dl, dr;
+};
+
 template <bool LDS>
-__device__ __forceinline__ bool test_word(const PassPtrs<LDS>& p, int idx, int rr, int si, int sj, int WW, int H,
-                                          uint32_t flip)
+__device__ __forceinline__ WordNbhd load_word(const PassPtrs<LDS>& p, int idx, int rr, int si, int WW, int H)
 {
+    WordNbhd n;
     const int my_w = idx - rr * WW;
-    const bool hasL = my_w > 0, hasR = my_w + 1 < WW;
-    const uint32_t scw = p.Ss[idx];
-    const uint32_t live = p.Ms[idx] & (scw ^ flip);
+    n.idx = idx;
+    n.hasL = my_w > 0;
+    n.hasR = my_w + 1 < WW;
     const int row = 2 * rr + si;
-    const bool hasN = row > 0, hasS = row + 1 < H;
-    const int iN = (si ? rr : rr - 1) * WW + my_w;  // row - 1 in the other parity
-    const int iS = (si ? rr + 1 : rr) * WW + my_w;  // row + 1
-    const uint32_t xc = p.Sx[idx];
-    const uint32_t xl = hasL ? p.Sx[idx - 1] : 0u;
-    const uint32_t xr = hasR ? p.Sx[idx + 1] : 0u;
-    const uint32_t nn = hasN ? p.Sy[iN] : 0u;
-    const uint32_t sv = hasS ? p.Sy[iS] : 0u;
-    const uint32_t nc = hasN ? p.Sxy[iN] : 0u;
-    const uint32_t nl = hasN && hasL ? p.Sxy[iN - 1] : 0u;
-    const uint32_t nr = hasN && hasR ? p.Sxy[iN + 1] : 0u;
-    const uint32_t dc = hasS ? p.Sxy[iS] : 0u;
-    const uint32_t dl = hasS && hasL ? p.Sxy[iS - 1] : 0u;
-    const uint32_t dr = hasS && hasR ? p.Sxy[iS + 1] : 0u;
+    n.hasN = row > 0;
+    n.hasS = row + 1 < H;
+    n.iN = (si ? rr : rr - 1) * WW + my_w;  // row - 1 in the other parity
+    n.iS = (si ? rr + 1 : rr) * WW + my_w;  // row + 1
+    n.scw = p.Ss[idx];
+    n.m = p.Ms[idx];
+    n.xc = p.Sx[idx];
+    n.xl = n.hasL ? p.Sx[idx - 1] : 0u;
+    n.xr = n.hasR ? p.Sx[idx + 1] : 0u;
+    n.nn = n.hasN ? p.Sy[n.iN] : 0u;
+    n.sv = n.hasS ? p.Sy[n.iS] : 0u;
+    n.nc = n.hasN ? p.Sxy[n.iN] : 0u;
+    n.nl = n.hasN && n.hasL ? p.Sxy[n.iN - 1] : 0u;
+    n.nr = n.hasN && n.hasR ? p.Sxy[n.iN + 1] : 0u;
+    n.dc = n.hasS ? p.Sxy[n.iS] : 0u;
+    n.dl = n.hasS && n.hasL ? p.Sxy[n.iS - 1] : 0u;
+    n.dr = n.hasS && n.hasR ? p.Sxy[n.iS + 1] : 0u;
+    return n;
+}
+
+// Flips the simple live candidates of a loaded word (thinning deletes,
+// thickening adds: live = M & (S ^ flip)) and flags every word whose test
+// reads a changed word. Returns whether a pixel changed.
+template <bool LDS>
+__device__ __forceinline__ bool apply_word(const PassPtrs<LDS>& p, const WordNbhd& n, int sj, uint32_t flip)
+{
+    const uint32_t live = n.m & (n.scw ^ flip);
     // column c of this sub-image is image column 2c + sj; its east neighbour
     // is column c (sj = 0) or c + 1 (sj = 1) of the other column parity, its
     // west one c - 1 or c
     uint32_t e, w, ne, nw2, se, sw;
     if (sj == 0) {
-        e = xc;
-        w = (xc << 1) | (xl >> 31);
-        ne = nc;
-        nw2 = (nc << 1) | (nl >> 31);
-        se = dc;
-        sw = (dc << 1) | (dl >> 31);
+        e = n.xc;
+        w = (n.xc << 1) | (n.xl >> 31);
+        ne = n.nc;
+        nw2 = (n.nc << 1) | (n.nl >> 31);
+        se = n.dc;
+        sw = (n.dc << 1) | (n.dl >> 31);
     } else {
-        e = (xc >> 1) | (xr << 31);
-        w = xc;
-        ne = (nc >> 1) | (nr << 31);
-        nw2 = nc;
-        se = (dc >> 1) | (dr << 31);
-        sw = dc;
+        e = (n.xc >> 1) | (n.xr << 31);
+        w = n.xc;
+        ne = (n.nc >> 1) | (n.nr << 31);
+        nw2 = n.nc;
+        se = (n.dc >> 1) | (n.dr << 31);
+        sw = n.dc;
     }
-    const uint32_t del = live & simple_bits<uint32_t>(e, ne, nn, nw2, w, sw, sv, se);
+    const uint32_t del = live & simple_bits<uint32_t>(e, ne, n.nn, nw2, w, sw, n.sv, se);
     if (!del)
         return false;
-    p.Ss[idx] = scw ^ del;
+    const int idx = n.idx, iN = n.iN, iS = n.iS;
+    p.Ss[idx] = n.scw ^ del;
     p.Dx[idx] = 1;
-    if (hasL)
+    if (n.hasL)
         p.Dx[idx - 1] = 1;
-    if (hasR)
+    if (n.hasR)
         p.Dx[idx + 1] = 1;
-    if (hasN) {
+    if (n.hasN) {
         p.Dy[iN] = 1;
         p.Dxy[iN] = 1;
-        if (hasL)
+        if (n.hasL)
             p.Dxy[iN - 1] = 1;
-        if (hasR)
+        if (n.hasR)
             p.Dxy[iN + 1] = 1;
     }
-    if (hasS) {
+    if (n.hasS) {
         p.Dy[iS] = 1;
         p.Dxy[iS] = 1;
-        if (hasL)
+        if (n.hasL)
             p.Dxy[iS - 1] = 1;
-        if (hasR)
+        if (n.hasR)
             p.Dxy[iS + 1] = 1;
     }
     return true;
+}
+
+// Tests the activated candidates of word idx (row rr of sub-image (si, sj))
+// and flips the simple ones; see load_word and apply_word.
+template <bool LDS>
+__device__ __forceinline__ bool test_word(const PassPtrs<LDS>& p, int idx, int rr, int si, int sj, int WW, int H,
+                                          uint32_t flip)
+{
+    return apply_word(p, load_word(p, idx, rr, si, WW, H), sj, flip);
 }
 
 // Rounds of the four subfield passes (even,even) (even,odd) (odd,even)

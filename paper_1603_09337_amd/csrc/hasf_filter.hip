@@ -368,11 +368,34 @@ __device__ __forceinline__ bool grid_sync(GridSync& gs, int* s_ok)
     return *s_ok != 0;
 }
 
+// flagged words a workgroup lists per chunk of a pass: GRID_CHUNK flag
+// words (4 bytes each) per thread
+constexpr int GRID_CHUNK = 4;
+constexpr int GRID_LIST = GRID_CHUNK * 4 * BLOCK;
+
+// exclusive prefix over the wave of v in [0, 31]; *total = sum over the wave
+__device__ __forceinline__ unsigned wave_prefix32(unsigned v, unsigned* total)
+{
+    const uint64_t lt = lanemask_lt();
+    unsigned pre = 0, tot = 0;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+        const uint64_t m = __ballot((v >> b) & 1u);
+        pre += (unsigned)__popcll(m & lt) << b;
+        tot += (unsigned)__popcll(m) << b;
+    }
+    *total = tot;
+    return pre;
+}
+
 // Rounds of the four subfield passes until a round changes nothing (the same
-// schedule as run_rounds); each thread scans 4 flag bytes of the pass's
-// sub-image at a time and tests its flagged live words at once.
+// schedule as run_rounds). A pass goes over its sub-image in chunks: each
+// thread loads GRID_CHUNK flag words at once (interleaved over the grid) and
+// lists its flagged words in the workgroup's LDS list; after a workgroup
+// barrier the list is tested densely, each word's loads issued together.
+// This keeps a pass at about two dependent global round trips.
 __device__ __forceinline__ bool rounds_grid(const Img<false>& g, GridSync& gs, int* s_ok, bool thin, Sched& sc,
-                                            int t0, int tn)
+                                            int t0, int tn, lds_u32* list, lds_u32* lcount)
 {
     const uint32_t flip = thin ? 0u : ~0u;
     CtlView v = ctl_view(gs);
@@ -389,18 +412,55 @@ __device__ __forceinline__ bool rounds_grid(const Img<false>& g, GridSync& gs, i
             const PassPtrs<false> pp = pass_ptrs(g, si, sj);
             glb_u32* D4 = (glb_u32*)(g.D + g.sub(si, sj));
             const int nw = ((g.H - si + 1) >> 1) * g.WW;
+            const int nw4 = (nw + 3) >> 2;
+            const int nchunk = (nw4 + GRID_CHUNK * tn - 1) / (GRID_CHUNK * tn);  // uniform
             bool changed = false;
-            for (int q4 = t0; 4 * q4 < nw; q4 += tn) {
-                const uint32_t f4 = D4[q4];
-                if (f4 == 0)
-                    continue;
-                D4[q4] = 0u;
+            for (int ch = 0; ch < nchunk; ++ch) {
+                uint32_t f4[GRID_CHUNK];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int q = 4 * q4 + j;
-                    if (((f4 >> (8 * j)) & 0xFFu) && q < nw && (pp.Ms[q] & (pp.Ss[q] ^ flip)))
+                for (int k = 0; k < GRID_CHUNK; ++k) {
+                    const int q4 = t0 + (ch * GRID_CHUNK + k) * tn;
+                    f4[k] = q4 < nw4 ? D4[q4] : 0u;
+                }
+                unsigned nl = 0;
+#pragma unroll
+                for (int k = 0; k < GRID_CHUNK; ++k) {
+                    if (f4[k]) {
+                        D4[t0 + (ch * GRID_CHUNK + k) * tn] = 0u;
+                        nl += __popc(f4[k] & 0x01010101u);
+                    }
+                }
+                // list counts alternate between chunks (sc.npass counts them);
+                // the other one is cleared once every thread has read it
+                const int cc = sc.npass++;
+                lds_u32* cnt = lcount + (cc & 1);
+                unsigned tot;
+                const unsigned off = wave_prefix32(nl, &tot);
+                unsigned base = 0;
+                if (tot) {
+                    if ((threadIdx.x & 63) == 0)
+                        base = __hip_atomic_fetch_add(cnt, tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    base = (unsigned)__builtin_amdgcn_readfirstlane((int)base) + off;
+#pragma unroll
+                    for (int k = 0; k < GRID_CHUNK; ++k) {
+                        const int q0 = 4 * (t0 + (ch * GRID_CHUNK + k) * tn);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if ((f4[k] >> (8 * j)) & 1u)
+                                list[base++] = (uint32_t)(q0 + j);
+                    }
+                }
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    lcount[(cc + 1) & 1] = 0u;
+                const int n = (int)*cnt;
+                for (int t = threadIdx.x; t < n; t += BLOCK) {
+                    const int q = (int)list[t];
+                    if (q < nw)
                         changed |= test_word(pp, q, q / g.WW, si, sj, g.WW, g.H, flip);
                 }
+                if (ch + 1 < nchunk)
+                    __syncthreads();  // the next chunk rewrites the list (the grid barrier ends the last)
             }
             const uint64_t chm = __ballot(changed);
             if (chm && (int)(threadIdx.x & 63) == __ffsll((long long)chm) - 1) {
@@ -424,13 +484,16 @@ __device__ __forceinline__ bool rounds_grid(const Img<false>& g, GridSync& gs, i
 // Levels in increasing order, as level_loop; the caller has cleared the
 // candidates and the control words.
 __device__ __forceinline__ bool level_loop_grid(const Img<false>& g, GridSync& gs, int* s_ok, bool thin, int nlev,
-                                                int t0, int tn)
+                                                int t0, int tn, lds_u32* list, lds_u32* lcount)
 {
     Sched sc;
     sc.serial = 0;
-    sc.npass = 0;
+    sc.npass = 0;  // here: chunks listed so far (selects the list count)
     for (int k = 0; k < 4; ++k)
         sc.consumed[k] = 0;
+    if (threadIdx.x == 0)
+        lcount[0] = lcount[1] = 0u;
+    __syncthreads();
     for (int k = 0; k < nlev; ++k) {
         const unsigned c = min(__hip_atomic_load(&gs.gc->cnt[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
                                (unsigned)g.NWD);
@@ -466,14 +529,15 @@ __device__ __forceinline__ bool level_loop_grid(const Img<false>& g, GridSync& g
                 ctl_wr(gs, CTL_PROD + b, ser);
         if (!grid_sync(gs, s_ok))
             return false;
-        if (!rounds_grid(g, gs, s_ok, thin, sc, t0, tn))
+        if (!rounds_grid(g, gs, s_ok, thin, sc, t0, tn, list, lcount))
             return false;
     }
     return true;
 }
 
 // The whole filter on one image, over the grid (as run_image).
-__device__ __forceinline__ bool run_image_grid(const ImgDesc* __restrict__ dp, GridCtl* gc, int* s_ok)
+__device__ __forceinline__ bool run_image_grid(const ImgDesc* __restrict__ dp, GridCtl* gc, int* s_ok,
+                                               lds_u32* list, lds_u32* lcount)
 {
     GridSync gs{gc, gridDim.x, 0u};
     const int t0 = blockIdx.x * BLOCK + threadIdx.x, tn = gridDim.x * BLOCK;
@@ -505,7 +569,7 @@ __device__ __forceinline__ bool run_image_grid(const ImgDesc* __restrict__ dp, G
             }
             if (!grid_sync(gs, s_ok))
                 return false;
-            if (!level_loop_grid(g, gs, s_ok, ph == HC_THIN || ph == HF_THIN, nlev, t0, tn))
+            if (!level_loop_grid(g, gs, s_ok, ph == HC_THIN || ph == HF_THIN, nlev, t0, tn, list, lcount))
                 return false;
             // every workgroup has read the counts of the levels it ran (a
             // workgroup still finishing its last round only reads zeros)
@@ -531,7 +595,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     const ImgDesc* __restrict__ dp, GridCtl* gc, unsigned* err_out)
 {
     __shared__ int s_ok;
-    if (!run_image_grid(dp, gc, &s_ok) && threadIdx.x == 0) {
+    __shared__ uint32_t list[GRID_LIST];
+    __shared__ uint32_t lcount[2];
+    if (!run_image_grid(dp, gc, &s_ok, (lds_u32*)list, (lds_u32*)lcount) && threadIdx.x == 0) {
         __hip_atomic_store(&gc->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (err_out)
             __hip_atomic_fetch_or(err_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
