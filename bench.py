@@ -22,6 +22,7 @@ Beside it, on the same GPU:
   those 64 frames;
 * edt: the exact squared EDT (hasf_edt_sq) of the 4096x4096 r=10 input, as
   HBM GB/s against the 8 TB/s peak;
+* large: the whole filter on that 4096x4096 r=10 image alone;
 * roofline: the batched filter kernel, bound by VALU integer lane operations
   (instruction counts from the committed rocprofv3 counter summary);
 * cpu_baseline: the CPU oracle on a small sample of the 512x512 images
@@ -111,6 +112,30 @@ def bench_edt(ctx, reps=20):
             "frac": round(bytes_ / t / HBM_PEAK, 4), "traffic": None, "us_per_call": round(t * 1e6, 1),
             "workload": "hasf_edt_sq 4096x4096, border is feature (the 4096x4096 r=10 input)",
             "bytes_per_call": bytes_}
+
+
+def bench_large(ctx, reps=3):
+    """The whole filter on the 4096x4096 r=10 image alone (grid path)."""
+    import torch
+    from paper_1603_09337_amd import synth
+    X, C, r = synth.workload_large()
+    src = torch.from_numpy(X).cuda()
+    d = src.clone()
+    ctx.filter(d, None, r)
+    ctx.sync()
+    stream = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        d.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.filter(d, None, r)
+        e1.record(stream)
+        ctx.sync()
+        ts.append(e0.elapsed_time(e1))
+    ms = min(ts)
+    return {"workload": "hasf 4096x4096 r=10, C empty, one image (grid of workgroups)", "ms": round(ms, 2),
+            "Mpixel_per_s": round(X.size / ms / 1e3, 2), "frames_per_s": round(1e3 / ms, 3)}
 
 
 def run_stream(srv, frames, arrivals):
@@ -351,6 +376,8 @@ def main():
 
     log("edt 4096x4096")
     edt = bench_edt(ctx)
+    log("filter 4096x4096 r=10")
+    large = bench_large(ctx)
 
     served = None
     if not a.no_serve:
@@ -393,6 +420,7 @@ def main():
         "served": served,
         "served_over_plain": (round(served["stream_512"]["frames_per_s"] / plain_fps, 2) if served else None),
         "edt": edt,
+        "large": large,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
