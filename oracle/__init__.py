@@ -63,6 +63,7 @@ def _load():
     lib.oracle_hf.argtypes = [U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.oracle_hf.restype = ctypes.c_long
     lib.oracle_hasf.argtypes = [U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int, U8P]
+    lib.oracle_hasf_cd.argtypes = [U8P, U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, U8P]
     lib.oracle_hasf.restype = ctypes.c_long
     lib.oracle_hasf_queue.argtypes = [U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.oracle_hasf_queue.restype = ctypes.c_long
@@ -172,15 +173,22 @@ def hf(X, i: int) -> np.ndarray:
     return x
 
 
-def hasf(X, C, r: int, stages: bool = False, queue: bool = False):
-    """HASF of order r; with stages=True also returns an (r, 4, H, W) stage dump."""
+def hasf(X, C, r: int, stages: bool = False, queue: bool = False, D=None, n: int = 8):
+    """HASF of order r (Sec. 2) with constraint sets C (kept object) and D (kept
+    background), for the connectivity pair (n, n-bar) = (8, 4) or (4, 8); with
+    stages=True also returns an (r, 4, H, W) stage dump."""
     x = np.ascontiguousarray(X, dtype=np.uint8).copy()
     c, cp = _opt_u8(C)
     H, W = x.shape
     if queue:
+        assert D is None and n == 8
         _check(_load().oracle_hasf_queue(x.ctypes.data_as(U8P), cp, H, W, r), "hasf_queue")
         return x
     st = np.zeros((max(r, 1), 4, H, W), dtype=np.uint8) if stages else None
-    _check(_load().oracle_hasf(x.ctypes.data_as(U8P), cp, H, W, r,
-                               st.ctypes.data_as(U8P) if st is not None else None), "hasf")
+    sp = st.ctypes.data_as(U8P) if st is not None else None
+    if D is None and n == 8:
+        _check(_load().oracle_hasf(x.ctypes.data_as(U8P), cp, H, W, r, sp), "hasf")
+    else:
+        d, dp = _opt_u8(D)
+        _check(_load().oracle_hasf_cd(x.ctypes.data_as(U8P), cp, dp, H, W, r, n, sp), "hasf_cd")
     return (x, st[:r]) if stages else x

@@ -384,16 +384,29 @@ static long subfield_schedule(int mode, uint8_t* S, const uint8_t* B, const uint
     return rounds;
 }
 
-static uint8_t g_lut84[256];
+static uint8_t g_lut84[256], g_lut48[256];
 static int g_lut_ready = 0;
 
-static const uint8_t* lut84(void)
+static void luts_init(void)
 {
     if (!g_lut_ready) {
         oracle_simple_lut(8, g_lut84);
+        oracle_simple_lut(4, g_lut48);
         g_lut_ready = 1;
     }
+}
+
+static const uint8_t* lut84(void)
+{
+    luts_init();
     return g_lut84;
+}
+
+/* simple points for the pair (n, n-bar) = (8, 4) or (4, 8) (Sec. 2) */
+static const uint8_t* lut_for(int n)
+{
+    luts_init();
+    return n == 4 ? g_lut48 : g_lut84;
 }
 
 /* Thinning with an explicit priority map (for tests). */
@@ -466,20 +479,24 @@ long oracle_homotopic_thicken(uint8_t* Y, const uint8_t* V, int H, int W)
 /* composition HASF = HF_r o HC_r o ... o HF_1 o HC_1).                      */
 /* ------------------------------------------------------------------------ */
 
-typedef long (*sched_fn)(int mode, uint8_t* S, const uint8_t* B, const uint32_t* P, int H, int W);
+typedef long (*sched_fn)(int mode, uint8_t* S, const uint8_t* B, const uint32_t* P, int H, int W,
+                         const uint8_t* lut);
 
-static long sched_subfield(int mode, uint8_t* S, const uint8_t* B, const uint32_t* P, int H, int W)
+static long sched_subfield(int mode, uint8_t* S, const uint8_t* B, const uint32_t* P, int H, int W,
+                           const uint8_t* lut)
 {
-    return subfield_schedule(mode, S, B, P, H, W, lut84());
+    return subfield_schedule(mode, S, B, P, H, W, lut);
 }
 
-static long queue_schedule(int mode, uint8_t* S, const uint8_t* B, const uint32_t* P, int H, int W);
+static long queue_schedule(int mode, uint8_t* S, const uint8_t* B, const uint32_t* P, int H, int W,
+                           const uint8_t* lut);
 
 typedef struct {
-    uint8_t* a;   /* N bytes */
-    uint8_t* b;   /* N bytes */
-    uint32_t* P;  /* N words */
-    sched_fn run; /* thinning / thickening schedule */
+    uint8_t* a;          /* N bytes */
+    uint8_t* b;          /* N bytes */
+    uint32_t* P;         /* N words */
+    sched_fn run;        /* thinning / thickening schedule */
+    const uint8_t* lut;  /* simple-point table of the connectivity pair */
 } work_t;
 
 /* HC_i with constraint C (C subset of X, NULL = empty). stage: 2 x N bytes or NULL. */
@@ -499,7 +516,7 @@ static long hc(uint8_t* X, const uint8_t* C, int H, int W, int i, work_t* w, uin
         K[p] = (X[p] && w->P[p] > r2) || (C && C[p]);
         Xs[p] = X[p];
     }
-    if ((rc = w->run(0, X, K, w->P, H, W)) < 0)
+    if ((rc = w->run(0, X, K, w->P, H, W, w->lut)) < 0)
         return rc;
     if (stage)
         memcpy(stage, X, N);
@@ -508,14 +525,15 @@ static long hc(uint8_t* X, const uint8_t* C, int H, int W, int i, work_t* w, uin
         return rc;
     for (size_t p = 0; p < N; ++p)
         K[p] = w->P[p] <= r2 && Xs[p];
-    if ((rc = w->run(1, X, K, w->P, H, W)) < 0)
+    if ((rc = w->run(1, X, K, w->P, H, W, w->lut)) < 0)
         return rc;
     if (stage)
         memcpy(stage + N, X, N);
     return 0;
 }
 
-static long hf(uint8_t* X, int H, int W, int i, work_t* w, uint8_t* stage)
+/* HF_i with background constraint D (D in the complement of X, NULL = empty). */
+static long hf(uint8_t* X, const uint8_t* D, int H, int W, int i, work_t* w, uint8_t* stage)
 {
     const size_t N = (size_t)H * W;
     const uint32_t r2 = (uint32_t)i * (uint32_t)i;
@@ -523,12 +541,12 @@ static long hf(uint8_t* X, int H, int W, int i, work_t* w, uint8_t* stage)
     uint8_t* Xs = w->b;
     long rc;
     memcpy(Xs, X, N);
-    /* L = delta_i(X) (inside the window), priority = d2(., X) */
+    /* L = delta_i(X) n complement(D) (inside the window), priority = d2(., X) */
     if ((rc = oracle_edt_sq(X, H, W, 0, w->P)))
         return rc;
     for (size_t p = 0; p < N; ++p)
-        L[p] = w->P[p] <= r2;
-    if ((rc = w->run(1, X, L, w->P, H, W)) < 0)
+        L[p] = w->P[p] <= r2 && !(D && D[p]);
+    if ((rc = w->run(1, X, L, w->P, H, W, w->lut)) < 0)
         return rc;
     if (stage)
         memcpy(stage, X, N);
@@ -539,7 +557,7 @@ static long hf(uint8_t* X, int H, int W, int i, work_t* w, uint8_t* stage)
         return rc;
     for (size_t p = 0; p < N; ++p)
         L[p] = (X[p] && w->P[p] > r2) || Xs[p];
-    if ((rc = w->run(0, X, L, w->P, H, W)) < 0)
+    if ((rc = w->run(0, X, L, w->P, H, W, w->lut)) < 0)
         return rc;
     if (stage)
         memcpy(stage + N, X, N);
@@ -549,6 +567,7 @@ static long hf(uint8_t* X, int H, int W, int i, work_t* w, uint8_t* stage)
 static int work_alloc(work_t* w, size_t N, sched_fn run)
 {
     w->run = run;
+    w->lut = lut84();
     w->a = (uint8_t*)malloc(N);
     w->b = (uint8_t*)malloc(N);
     w->P = (uint32_t*)malloc(sizeof(uint32_t) * N);
@@ -602,39 +621,48 @@ long oracle_hf(uint8_t* X, int H, int W, int i)
     long rc = work_alloc(&w, N, sched_subfield);
     if (rc)
         return rc;
-    rc = hf(X, H, W, i, &w, NULL);
+    rc = hf(X, NULL, H, W, i, &w, NULL);
     work_free(&w);
     return rc < 0 ? rc : 0;
 }
 
-static long hasf_core(uint8_t* X, const uint8_t* C, int H, int W, int r, uint8_t* stages, sched_fn run)
+static long hasf_core(uint8_t* X, const uint8_t* C, const uint8_t* D, int H, int W, int r, int n,
+                      uint8_t* stages, sched_fn run)
 {
-    if (H < 1 || W < 1 || r < 0)
+    if (H < 1 || W < 1 || r < 0 || (n != 8 && n != 4))
         return ORACLE_EINVAL;
     const size_t N = (size_t)H * W;
     normalise(X, N);
+    /* C <- C n X and D <- D \ X (Sec. 2: C is a subset of X, D of its complement) */
     uint8_t* Cn = NULL;
-    if (C) {
+    uint8_t* Dn = NULL;
+    if (C || D) {
         Cn = (uint8_t*)malloc(N);
-        if (!Cn)
+        Dn = (uint8_t*)malloc(N);
+        if (!Cn || !Dn) {
+            free(Cn); free(Dn);
             return ORACLE_ENOMEM;
-        for (size_t p = 0; p < N; ++p)
-            Cn[p] = C[p] && X[p];
+        }
+        for (size_t p = 0; p < N; ++p) {
+            Cn[p] = C && C[p] && X[p];
+            Dn[p] = D && D[p] && !X[p];
+        }
     }
     work_t w;
     long rc = work_alloc(&w, N, run);
     if (rc) {
-        free(Cn);
+        free(Cn); free(Dn);
         return rc;
     }
+    w.lut = lut_for(n);
     for (int i = 1; i <= r && rc == 0; ++i) {
         uint8_t* st = stages ? stages + (size_t)(i - 1) * 4 * N : NULL;
-        rc = hc(X, Cn, H, W, i, &w, st);
+        rc = hc(X, C ? Cn : NULL, H, W, i, &w, st);
         if (rc == 0)
-            rc = hf(X, H, W, i, &w, st ? st + 2 * N : NULL);
+            rc = hf(X, D ? Dn : NULL, H, W, i, &w, st ? st + 2 * N : NULL);
     }
     work_free(&w);
-    free(Cn);
+    free(Cn); free(Dn);
     return rc;
 }
 
@@ -644,13 +672,21 @@ static long hasf_core(uint8_t* X, const uint8_t* C, int H, int W, int r, uint8_t
  * and after the filling. */
 long oracle_hasf(uint8_t* X, const uint8_t* C, int H, int W, int r, uint8_t* stages)
 {
-    return hasf_core(X, C, H, W, r, stages, sched_subfield);
+    return hasf_core(X, C, NULL, H, W, r, 8, stages, sched_subfield);
+}
+
+/* HASF^{C,D} of order r for the connectivity pair (n, n-bar), n = 8: (8,4),
+ * n = 4: (4,8) (Sec. 2): the cutting keeps C (C <- C n X), the filling never
+ * adds a point of D (D <- D \ X), so D stays background. NULL = empty. */
+long oracle_hasf_cd(uint8_t* X, const uint8_t* C, const uint8_t* D, int H, int W, int r, int n, uint8_t* stages)
+{
+    return hasf_core(X, C, D, H, W, r, n, stages, sched_subfield);
 }
 
 /* The same filter with the queue-ordered schedule below. */
 long oracle_hasf_queue(uint8_t* X, const uint8_t* C, int H, int W, int r)
 {
-    return hasf_core(X, C, H, W, r, NULL, queue_schedule);
+    return hasf_core(X, C, NULL, H, W, r, 8, NULL, queue_schedule);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -702,10 +738,10 @@ static hnode hpop(hnode* h, size_t* n)
     return top;
 }
 
-static long queue_schedule(int mode, uint8_t* S, const uint8_t* B, const uint32_t* P, int H, int W)
+static long queue_schedule(int mode, uint8_t* S, const uint8_t* B, const uint32_t* P, int H, int W,
+                           const uint8_t* lut)
 {
     const size_t N = (size_t)H * W;
-    const uint8_t* lut = lut84();
     /* a pixel is queued at most once at a time: heap size <= N */
     hnode* heap = (hnode*)malloc(sizeof(hnode) * (N + 1));
     uint8_t* inq = (uint8_t*)calloc(N, 1);
@@ -751,10 +787,10 @@ static long queue_schedule(int mode, uint8_t* S, const uint8_t* B, const uint32_
 
 long oracle_thin_queue_p(uint8_t* S, const uint8_t* K, const uint32_t* P, int H, int W)
 {
-    return queue_schedule(0, S, K, P, H, W);
+    return queue_schedule(0, S, K, P, H, W, lut84());
 }
 
 long oracle_thicken_queue_p(uint8_t* S, const uint8_t* V, const uint32_t* P, int H, int W)
 {
-    return queue_schedule(1, S, V, P, H, W);
+    return queue_schedule(1, S, V, P, H, W, lut84());
 }

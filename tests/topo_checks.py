@@ -185,3 +185,34 @@ def sequential_schedule(mode: int, S: np.ndarray, B, P: np.ndarray) -> np.ndarra
             if not changed:
                 break
     return S
+
+
+# the (4,8) pair: object 4-adjacency, background 8-adjacency (Sec. 2)
+def components4(X: np.ndarray) -> int:
+    return ndimage.label(X != 0, FOUR)[1]
+
+
+def components8_complement(X: np.ndarray) -> int:
+    """8-components of the complement, the outside of the window included."""
+    P = np.ones((X.shape[0] + 2, X.shape[1] + 2), dtype=np.uint8)
+    P[1:-1, 1:-1] = X == 0
+    return ndimage.label(P, EIGHT)[1]
+
+
+def euler48_quads(X: np.ndarray) -> int:
+    """Euler number of X under 4-adjacency from Gray's 2x2 quad counts:
+    E = (n(Q1) - n(Q3) + 2 n(QD)) / 4 on the image padded with background."""
+    P = np.zeros((X.shape[0] + 2, X.shape[1] + 2), dtype=np.int32)
+    P[1:-1, 1:-1] = X != 0
+    a, b, c, d = P[:-1, :-1], P[:-1, 1:], P[1:, :-1], P[1:, 1:]
+    s = a + b + c + d
+    q1 = int((s == 1).sum())
+    q3 = int((s == 3).sum())
+    qd = int(((s == 2) & (a == d)).sum())
+    e4 = q1 - q3 + 2 * qd
+    assert e4 % 4 == 0
+    return e4 // 4
+
+
+def topology48(X: np.ndarray):
+    return components4(X), components8_complement(X), euler48_quads(X)
