@@ -149,13 +149,27 @@ hasf_status hasf_homotopic_thicken(hasf_ctx* ctx, uint8_t* Y, const uint8_t* V, 
 hasf_status hasf_filter(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, int H, int W, int64_t ld,
                         int r);
 
-/* One image of a batch. */
+/*
+ * HASF^{C,D} (Sec. 2): as hasf_filter, with a background constraint set D --
+ * the filling's thickening never adds a point of D, so D stays background
+ * (D is intersected with the complement of X; D may be NULL: empty) -- and
+ * the connectivity pair chosen by conn: 8 (or 0) for 8-connected objects and
+ * a 4-connected background, 4 for 4-connected objects and an 8-connected
+ * background (the simple points of (4,8) are those of (8,4) for the
+ * complemented neighbourhood). D shares X's pitch. HASF_EINVAL for other conn.
+ */
+hasf_status hasf_filter_cd(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, const uint8_t* D, int H, int W,
+                           int64_t ld, int r, int conn);
+
+/* One image of a batch (zero-initialise: D = NULL and conn = 0 give hasf_filter). */
 typedef struct {
     uint8_t* X;        /* device, in/out */
     const uint8_t* C;  /* device or NULL */
     int H, W;
     int64_t ld;
     int r;
+    const uint8_t* D;  /* device or NULL: background constraint set, as in hasf_filter_cd */
+    int conn;          /* 0 or 8: (8,4); 4: (4,8) */
 } hasf_image;
 
 /*

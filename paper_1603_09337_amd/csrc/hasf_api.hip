@@ -338,6 +338,11 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
             set_err(ctx, "%s: image %d: r = %d outside [0, %d]", what, k, imgs[k].r, HASF_R_MAX);
             return HASF_EINVAL;
         }
+        if (imgs[k].conn != 0 && imgs[k].conn != 8 && imgs[k].conn != 4) {
+            set_err(ctx, "%s: image %d: conn = %d (0 or 8: the (8,4) pair; 4: the (4,8) pair)", what, k,
+                    imgs[k].conn);
+            return HASF_EINVAL;
+        }
     }
     if (n == 0)
         return HASF_OK;
@@ -379,6 +384,9 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
         d.W = im.W;
         d.r = im.r;
         d.lds = L.lds ? 1 : 0;
+        d.D = im.D;
+        d.conn4 = im.conn == 4 ? 1 : 0;
+        d.pad_ = 0;
         // offsets for now; rebased after allocation
         d.gplanes = (uint64_t*)bytes;
         bytes += L.planes_bytes;
@@ -474,6 +482,12 @@ extern "C" {
 
 hasf_status hasf_filter(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, int H, int W, int64_t ld, int r)
 {
+    return hasf_filter_cd(ctx, X, C, nullptr, H, W, ld, r, 8);
+}
+
+hasf_status hasf_filter_cd(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, const uint8_t* D, int H, int W,
+                           int64_t ld, int r, int conn)
+{
     hasf_image im;
     im.X = X;
     im.C = C;
@@ -481,6 +495,8 @@ hasf_status hasf_filter(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, int H, int 
     im.W = W;
     im.ld = ld;
     im.r = r;
+    im.D = D;
+    im.conn = conn;
     return run_images(ctx, &im, 1, "hasf_filter");
 }
 

@@ -126,9 +126,12 @@ struct ImgDesc {
     long long ld;
     int H, W, r;
     int lds;            // 1: S and M planes in LDS; 0: in gplanes
-    uint64_t* gplanes;  // S, M (when lds == 0), A (saved set), K (constraint)
+    uint64_t* gplanes;  // S, M (when lds == 0), A (saved set), K (constraint), D (background constraint)
     uint32_t* ent_idx;  // level entries: word index, levels(r) x words
     uint64_t* ent_msk;  // level entries: candidate bits
+    const uint8_t* D;   // background constraint set (same pitch as X) or NULL
+    int conn4;          // 1: the (4,8) connectivity pair; 0: (8,4)
+    int pad_;
 };
 
 // Control block of one image filtered by a grid of workgroups (device memory,
@@ -149,7 +152,7 @@ struct GridCtl {
 struct ImageLayout {
     bool lds;
     size_t lds_bytes;     // dynamic LDS the image needs (0 if it is in global memory)
-    size_t planes_bytes;  // [state (unless LDS) | A | K]
+    size_t planes_bytes;  // [state (unless LDS) | A | K | D]
     size_t idx_bytes, msk_bytes;
     size_t total() const { return planes_bytes + idx_bytes + msk_bytes; }
 };
@@ -168,7 +171,7 @@ inline ImageLayout image_layout(int H, int W, int r, size_t lds_cap)
     L.lds = hasf_align256(state_bytes(H, W, true)) <= lds_cap;
     const size_t sb = hasf_align256(state_bytes(H, W, L.lds));
     L.lds_bytes = L.lds ? sb : 0;
-    L.planes_bytes = hasf_align256((L.lds ? 0 : sb) + 2 * NWD * 8);
+    L.planes_bytes = hasf_align256((L.lds ? 0 : sb) + 3 * NWD * 8);
     const size_t nlev = (size_t)(r > 0 ? hasf_levels(r) : 1);
     L.idx_bytes = hasf_align256(nlev * NWD * 4);
     L.msk_bytes = hasf_align256(nlev * NWD * 8);

@@ -67,11 +67,14 @@ struct Img {
     lds_i32* ctl; // control words in LDS, see run_rounds
     glb_u64* A;   // set saved before the phase (row-major)
     glb_u64* K;   // constraint set (row-major)
+    glb_u64* Dp;  // background constraint set \ X (row-major)
     glb_u32* eidx;
     glb_u64* emsk;
     int H, W, WW, NWD, HH, SUB;
     uint64_t lastmask;  // valid bits of the last word of a row
     bool hasK;
+    bool hasD;
+    bool conn4;  // the (4,8) pair
 
     __device__ __forceinline__ int sub(int si, int sj) const { return (si * 2 + sj) * SUB; }
 };
@@ -158,6 +161,18 @@ __device__ void pack_rows(const uint8_t* __restrict__ X, const uint8_t* __restri
         if (K)
             K[q] = k & m;
     }
+}
+
+// The background constraint set minus the object: D's bits packed into Dp,
+// then the bits of X (R, packed by the same threads) cleared.
+template <typename PR>
+__device__ void pack_background(const uint8_t* __restrict__ D, long long ld, int H, int W, PR R, glb_u64* Dp,
+                                int t0, int tn)
+{
+    pack_rows(D, (const uint8_t*)nullptr, ld, H, W, Dp, (glb_u64*)nullptr, t0, tn);
+    const int NWD = H * ((W + 63) >> 6);
+    for (int q = t0; q < NWD; q += tn)
+        Dp[q] &= ~R[q];
 }
 
 template <typename PR>
@@ -366,9 +381,12 @@ __device__ __forceinline__ WordNbhd load_word(const PassPtrs<LDS>& p, int idx, i
 
 // Flips the simple live candidates of a loaded word (thinning deletes,
 // thickening adds: live = M & (S ^ flip)) and flags every word whose test
-// reads a changed word. Returns whether a pixel changed.
+// reads a changed word. Returns whether a pixel changed. conn4: the (4,8)
+// pair, whose simple points are the (8,4) ones of the complemented
+// neighbourhood (the outside of the window, background, becomes object).
 template <bool LDS>
-__device__ __forceinline__ bool apply_word(const PassPtrs<LDS>& p, const WordNbhd& n, int sj, uint32_t flip)
+__device__ __forceinline__ bool apply_word(const PassPtrs<LDS>& p, const WordNbhd& n, int sj, uint32_t flip,
+                                           bool conn4 = false)
 {
     const uint32_t live = n.m & (n.scw ^ flip);
     // column c of this sub-image is image column 2c + sj; its east neighbour
@@ -390,7 +408,18 @@ __device__ __forceinline__ bool apply_word(const PassPtrs<LDS>& p, const WordNbh
         se = (n.dc >> 1) | (n.dr << 31);
         sw = n.dc;
     }
-    const uint32_t del = live & simple_bits<uint32_t>(e, ne, n.nn, nw2, w, sw, n.sv, se);
+    uint32_t nn = n.nn, sv = n.sv;
+    if (conn4) {
+        e = ~e;
+        ne = ~ne;
+        nn = ~nn;
+        nw2 = ~nw2;
+        w = ~w;
+        sw = ~sw;
+        sv = ~sv;
+        se = ~se;
+    }
+    const uint32_t del = live & simple_bits<uint32_t>(e, ne, nn, nw2, w, sw, sv, se);
     if (!del)
         return false;
     const int idx = n.idx, iN = n.iN, iS = n.iS;
@@ -423,9 +452,9 @@ __device__ __forceinline__ bool apply_word(const PassPtrs<LDS>& p, const WordNbh
 // and flips the simple ones; see load_word and apply_word.
 template <bool LDS>
 __device__ __forceinline__ bool test_word(const PassPtrs<LDS>& p, int idx, int rr, int si, int sj, int WW, int H,
-                                          uint32_t flip)
+                                          uint32_t flip, bool conn4 = false)
 {
-    return apply_word(p, load_word(p, idx, rr, si, WW, H), sj, flip);
+    return apply_word(p, load_word(p, idx, rr, si, WW, H), sj, flip, conn4);
 }
 
 // Rounds of the four subfield passes (even,even) (even,odd) (odd,even)
@@ -523,7 +552,7 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
                     --rr;
                 else if ((rr + 1) * WW <= idx)
                     ++rr;
-                changed_here |= test_word(pp, idx, rr, si, sj, WW, g.H, flip);
+                changed_here |= test_word(pp, idx, rr, si, sj, WW, g.H, flip, g.conn4);
             }
             // one lane per wave records the change (a same-address store from
             // many lanes would be serialised)

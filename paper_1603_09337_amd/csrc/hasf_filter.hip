@@ -59,7 +59,10 @@ __device__ __forceinline__ Img<LDS> make_img(const ImgDesc* __restrict__ dp, uin
         g.A = (glb_u64*)((glb_u8*)gp + sb);
         g.K = g.A + NWD;
     }
+    g.Dp = g.K + NWD;
     g.hasK = dp->C != nullptr;
+    g.hasD = dp->D != nullptr;
+    g.conn4 = dp->conn4 != 0;
     g.eidx = (glb_u32*)dp->ent_idx;
     g.emsk = (glb_u64*)dp->ent_msk;
     return g;
@@ -128,7 +131,8 @@ __device__ __attribute__((noinline)) void stage(const ImgDesc* __restrict__ dp, 
                 base = ~s & g.A[q] & valid;
                 break;
             case HF_THICKEN:
-                base = ~s & valid;
+                // the filling never adds a point of the background constraint
+                base = ~s & valid & ~(g.hasD ? g.Dp[q] : 0ull);
                 g.A[q] = s;
                 break;
             default:
@@ -251,6 +255,8 @@ __device__ __attribute__((noinline)) void run_image(const ImgDesc* __restrict__ 
 {
     const Img<LDS> g = make_img<LDS>(dp, smem, ctl);
     pack_rows(dp->X, dp->C, dp->ld, g.H, g.W, g.R, g.hasK ? g.K : nullptr, threadIdx.x, BLOCK);
+    if (g.hasD)
+        pack_background(dp->D, dp->ld, g.H, g.W, g.R, g.Dp, threadIdx.x, BLOCK);
     for (int k = threadIdx.x; k < HASF_LEVELS_MAX; k += BLOCK)
         cnt[k] = 0;
     __syncthreads();
@@ -457,7 +463,7 @@ __device__ __forceinline__ bool rounds_grid(const Img<false>& g, GridSync& gs, i
                 for (int t = threadIdx.x; t < n; t += BLOCK) {
                     const int q = (int)list[t];
                     if (q < nw)
-                        changed |= test_word(pp, q, q / g.WW, si, sj, g.WW, g.H, flip);
+                        changed |= test_word(pp, q, q / g.WW, si, sj, g.WW, g.H, flip, g.conn4);
                 }
                 if (ch + 1 < nchunk)
                     __syncthreads();  // the next chunk rewrites the list (the grid barrier ends the last)
@@ -543,6 +549,8 @@ __device__ __forceinline__ bool run_image_grid(const ImgDesc* __restrict__ dp, G
     const int t0 = blockIdx.x * BLOCK + threadIdx.x, tn = gridDim.x * BLOCK;
     const Img<false> g = make_img<false>(dp, nullptr, nullptr);
     pack_rows(dp->X, dp->C, dp->ld, g.H, g.W, g.R, g.hasK ? g.K : nullptr, t0, tn);
+    if (g.hasD)
+        pack_background(dp->D, dp->ld, g.H, g.W, g.R, g.Dp, t0, tn);
     if (!grid_sync(gs, s_ok))
         return false;
     rows_to_sub(g, t0, tn);

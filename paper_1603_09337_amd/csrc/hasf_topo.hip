@@ -76,7 +76,10 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     glb_u64* Bp = (glb_u64*)(gp + boff);  // row-major bits of B
     g.A = nullptr;
     g.K = nullptr;
+    g.Dp = nullptr;
     g.hasK = false;
+    g.hasD = false;
+    g.conn4 = false;
     g.eidx = nullptr;
     g.emsk = nullptr;
     const int N = a.H * a.W;

@@ -41,7 +41,7 @@ class _Opts(ctypes.Structure):
 
 class _Image(ctypes.Structure):
     _fields_ = [("X", ctypes.c_void_p), ("C", ctypes.c_void_p), ("H", ctypes.c_int), ("W", ctypes.c_int),
-                ("ld", ctypes.c_int64), ("r", ctypes.c_int)]
+                ("ld", ctypes.c_int64), ("r", ctypes.c_int), ("D", ctypes.c_void_p), ("conn", ctypes.c_int)]
 
 
 class _ServeOpts(ctypes.Structure):
@@ -86,9 +86,12 @@ _lib.hasf_edt_sq.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int6
 _lib.hasf_homotopic_thin.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64]
 _lib.hasf_homotopic_thicken.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64]
 _lib.hasf_filter.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int]
+_lib.hasf_filter_cd.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                                ctypes.c_int]
 _lib.hasf_filter_batch.argtypes = [_vp, ctypes.POINTER(_Image), ctypes.c_int]
 for _f in ("hasf_create", "hasf_set_stream", "hasf_sync", "hasf_simple_lut", "hasf_edt_sq",
-           "hasf_homotopic_thin", "hasf_homotopic_thicken", "hasf_filter", "hasf_filter_batch"):
+           "hasf_homotopic_thin", "hasf_homotopic_thicken", "hasf_filter", "hasf_filter_cd",
+           "hasf_filter_batch"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -109,6 +112,19 @@ def simple_lut(n: int = 8):
     if st != HASF_OK:
         raise HasfError(st, _lib.hasf_last_error(None).decode())
     return [(bits[m >> 5] >> (m & 31)) & 1 for m in range(256)]
+
+
+def _image(item, tag=""):
+    """hasf_image for (X, C, r) or (X, C, r, D, conn)."""
+    X, C, r = item[0], item[1], item[2]
+    D = item[3] if len(item) > 3 else None
+    conn = item[4] if len(item) > 4 else 0
+    H, W, ld = _img(X, "X" + tag)
+    for name, T in (("C", C), ("D", D)):
+        if T is not None and (T.shape != X.shape or T.stride(0) != ld):
+            raise ValueError("%s%s must match X's shape and pitch" % (name, tag))
+    return _Image(X.data_ptr(), C.data_ptr() if C is not None else None, H, W, ld, r,
+                  D.data_ptr() if D is not None else None, conn)
 
 
 def _ptr(t):
@@ -181,22 +197,25 @@ class Context:
         self._check(_lib.hasf_homotopic_thicken(self._h, _ptr(Y), _ptr(V), H, W, ld))
         return Y
 
-    def filter(self, X, C=None, r: int = 1):
+    def filter(self, X, C=None, r: int = 1, D=None, conn: int = 8):
+        """hasf_filter (D None and conn 8) or hasf_filter_cd."""
         H, W, ld = _img(X, "X")
-        if C is not None and (C.shape != X.shape or C.stride(0) != ld):
-            raise ValueError("C must match X's shape and pitch")
+        for name, T in (("C", C), ("D", D)):
+            if T is not None and (T.shape != X.shape or T.stride(0) != ld):
+                raise ValueError("%s must match X's shape and pitch" % name)
         self._stream()
-        self._check(_lib.hasf_filter(self._h, _ptr(X), _ptr(C), H, W, ld, r))
+        if D is None and conn == 8:
+            self._check(_lib.hasf_filter(self._h, _ptr(X), _ptr(C), H, W, ld, r))
+        else:
+            self._check(_lib.hasf_filter_cd(self._h, _ptr(X), _ptr(C), _ptr(D), H, W, ld, r, conn))
         return X
 
     def plan_batch(self, items):
-        """Prepare the descriptor array of a batch once (the tensors must stay alive)."""
+        """Prepare the descriptor array of a batch once (the tensors must stay alive).
+        items: (X, C or None, r) or (X, C or None, r, D or None, conn)."""
         arr = (_Image * max(1, len(items)))()
-        for k, (X, C, r) in enumerate(items):
-            H, W, ld = _img(X, "X[%d]" % k)
-            if C is not None and (C.shape != X.shape or C.stride(0) != ld):
-                raise ValueError("C[%d] must match X's shape and pitch" % k)
-            arr[k] = _Image(X.data_ptr(), C.data_ptr() if C is not None else None, H, W, ld, r)
+        for k, it in enumerate(items):
+            arr[k] = _image(it, "[%d]" % k)
         return (arr, len(items), list(items))
 
     def run_plan(self, plan):
@@ -205,16 +224,13 @@ class Context:
         self._check(_lib.hasf_filter_batch(self._h, arr, n))
 
     def filter_batch(self, items):
-        """items: sequence of (X, C or None, r)."""
+        """items: sequence of (X, C or None, r) or (X, C or None, r, D or None, conn)."""
         arr = (_Image * max(1, len(items)))()
-        for k, (X, C, r) in enumerate(items):
-            H, W, ld = _img(X, "X[%d]" % k)
-            if C is not None and (C.shape != X.shape or C.stride(0) != ld):
-                raise ValueError("C[%d] must match X's shape and pitch" % k)
-            arr[k] = _Image(X.data_ptr(), C.data_ptr() if C is not None else None, H, W, ld, r)
+        for k, it in enumerate(items):
+            arr[k] = _image(it, "[%d]" % k)
         self._stream()
         self._check(_lib.hasf_filter_batch(self._h, arr, len(items)))
-        return [X for X, _, _ in items]
+        return [it[0] for it in items]
 
 
 class Server:
@@ -233,24 +249,21 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit(self, X, C=None, r: int = 1, check: bool = True):
+    def submit(self, X, C=None, r: int = 1, check: bool = True, D=None, conn: int = 0):
         """Queue a frame; returns its ticket (or the status when check=False and it fails)."""
-        H, W, ld = _img(X, "X")
-        if C is not None and (C.shape != X.shape or C.stride(0) != ld):
-            raise ValueError("C must match X's shape and pitch")
-        im = _Image(X.data_ptr(), C.data_ptr() if C is not None else None, H, W, ld, r)
+        im = _image((X, C, r, D, conn))
         t = ctypes.c_uint64()
         st = _lib.hasf_serve_submit(self._h, ctypes.byref(im), ctypes.byref(t))
         if st != HASF_OK:
             if check:
                 raise HasfError(st, "hasf_serve_submit")
             return st
-        self._keep[t.value] = (X, C)
+        self._keep[t.value] = (X, C, D)
         return t.value
 
-    def submit_raw(self, ptr, H, W, ld, r, cptr=None):
+    def submit_raw(self, ptr, H, W, ld, r, cptr=None, dptr=None, conn=0):
         """Queue a frame given by device pointer (the caller keeps it alive); returns (status, ticket)."""
-        im = _Image(ptr, cptr, H, W, ld, r)
+        im = _Image(ptr, cptr, H, W, ld, r, dptr, conn)
         t = ctypes.c_uint64()
         st = _lib.hasf_serve_submit(self._h, ctypes.byref(im), ctypes.byref(t))
         return st, t.value
