@@ -12,7 +12,8 @@
 //   edt_colcarry  16 threads per column: for every segment, the nearest
 //                 feature row above the segment and below it (a prefix-max /
 //                 suffix-min over the segment masks, in 16 chunks combined
-//                 through LDS).
+//                 through LDS; with at most 8 segments per chunk the masks
+//                 stay in registers between the scan and the writes).
 //   edt_rows32    one workgroup per strip of rows: g^2 of the strip from the
 //                 masks and carries (O(1) per pixel with clz/ctz), kept in
 //                 LDS as uint32 with "infinity" columns padding each row,
@@ -42,6 +43,7 @@ constexpr int PAD = 16;  // "infinity" columns on each side of a uint32 strip ro
 constexpr int NO_ROW_BELOW = 0x7FFFFFFF;
 constexpr int CARRY_GROUPS = 16;  // threads per column in edt_colcarry
 constexpr int CARRY_COLS = 16;    // columns per edt_colcarry workgroup
+constexpr int CARRY_REG = 8;      // segments per thread kept in registers by edt_colcarry
 
 // one thread per 4 columns and 32-row segment: the segment's features as masks
 __global__ __launch_bounds__(256) void edt_colmask(const uint8_t* __restrict__ F, long long ld, int H, int W,
@@ -96,6 +98,48 @@ __global__ __launch_bounds__(CARRY_COLS* CARRY_GROUPS) void edt_colcarry(const u
     const int G = (nseg + CARRY_GROUPS - 1) / CARRY_GROUPS;
     const int s0 = grp * G, s1 = min(nseg, s0 + G);
     int last = -1, first = NO_ROW_BELOW;
+    if (G <= CARRY_REG) {
+        // few segments per thread (H <= CARRY_REG * CARRY_GROUPS * 32): the
+        // masks stay in registers for the two writing passes
+        uint32_t mr[CARRY_REG];
+#pragma unroll
+        for (int k = 0; k < CARRY_REG; ++k)
+            mr[k] = (c < W && s0 + k < s1) ? mask[(size_t)(s0 + k) * W + c] : 0u;
+#pragma unroll
+        for (int k = 0; k < CARRY_REG; ++k)
+            if (mr[k]) {
+                last = (s0 + k) * SEG + 31 - __clz(mr[k]);
+                if (first == NO_ROW_BELOW)
+                    first = (s0 + k) * SEG + __ffs(mr[k]) - 1;
+            }
+        glast[grp][lc] = last;
+        gfirst[grp][lc] = first;
+        __syncthreads();
+        if (c >= W)
+            return;
+        int up = -1, dn = NO_ROW_BELOW;
+        for (int k = 0; k < grp; ++k)
+            up = max(up, glast[k][lc]);
+        for (int k = CARRY_GROUPS - 1; k > grp; --k)
+            dn = min(dn, gfirst[k][lc]);
+#pragma unroll
+        for (int k = 0; k < CARRY_REG; ++k) {
+            if (s0 + k >= s1)
+                break;
+            above[(size_t)(s0 + k) * W + c] = up;
+            if (mr[k])
+                up = (s0 + k) * SEG + 31 - __clz(mr[k]);
+        }
+#pragma unroll
+        for (int k = CARRY_REG - 1; k >= 0; --k) {
+            if (s0 + k >= s1)
+                continue;
+            below[(size_t)(s0 + k) * W + c] = dn;
+            if (mr[k])
+                dn = (s0 + k) * SEG + __ffs(mr[k]) - 1;
+        }
+        return;
+    }
     if (c < W) {
 #pragma unroll 8
         for (int s = s0; s < s1; ++s) {
@@ -214,6 +258,47 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows(const uint32_t* __restric
     }
 }
 
+// Phase 2 for column j of one row: min over k of (j - k)^2 + g2[k], where
+// gr points at the row's first column and has PAD columns of padding on each
+// side (G2_INF, or 0 with the frame). Columns are visited by increasing
+// |j - k| until (j - k)^2 alone reaches the best value found, beyond which no
+// column can improve it.
+__device__ __forceinline__ uint32_t row_min(const uint32_t* gr, int j, int W, int frame)
+{
+    uint32_t best = gr[j];
+    // d = 1 .. PAD, four per step, no bounds checks (with the frame, the zero
+    // padding supplies the distance to the left and right frame when it is
+    // within PAD columns)
+    int d = 1;
+#pragma unroll
+    for (int step = 0; step < PAD / 4; ++step) {
+        const int d0 = 1 + 4 * step;
+        if ((uint32_t)(d0 * d0) >= best)
+            break;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t dd = (uint32_t)((d0 + u) * (d0 + u));
+            best = min(best, __builtin_elementwise_add_sat(dd, gr[j - d0 - u]));
+            best = min(best, __builtin_elementwise_add_sat(dd, gr[j + d0 + u]));
+        }
+        d = d0 + 4;
+    }
+    // beyond the padding: checked, one column per side at a time
+    // (d, e < 2^16: 24-bit multiplies are exact)
+    if (frame && __umul24(d, d) < best) {
+        const uint32_t e = (uint32_t)min(j + 1, W - j);
+        best = min(best, __umul24(e, e));
+    }
+    for (; __umul24(d, d) < best && (j - d >= 0 || j + d < W); ++d) {
+        const uint32_t dd = __umul24(d, d);
+        if (j - d >= 0)
+            best = min(best, __builtin_elementwise_add_sat(dd, gr[j - d]));
+        if (j + d < W)
+            best = min(best, __builtin_elementwise_add_sat(dd, gr[j + d]));
+    }
+    return best;
+}
+
 // edt_rows with g^2 as uint32 in LDS: each strip row holds PAD columns, the
 // W values, PAD columns. Without the frame the padding is G2_INF (it cannot
 // improve best); with the frame every column outside the window is a feature
@@ -245,6 +330,8 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
         g2s[r * WP + (k < PAD ? k : W + k)] = pad;
     }
     int has = 0;
+    // the segment's rows of masks and carries: uniform bases and 32-bit
+    // offsets (loads with a scalar base address)
 #pragma unroll 4
     for (int c = threadIdx.x; c < W; c += blockDim.x) {
         const uint32_t m = mask[(size_t)s * W + c];
@@ -278,7 +365,8 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
             int g = min(i - ups[r], dn - i);
             if (frame)
                 g = min(g, min(i + 1, H - i));
-            g2s[r * WP + PAD + c] = g >= FAR ? G2_INF : (uint32_t)g * (uint32_t)g;
+            // g < 2^16 whenever it is not "none": a 24-bit multiply is exact
+            g2s[r * WP + PAD + c] = g >= FAR ? G2_INF : __umul24((uint32_t)g, (uint32_t)g);
         }
     }
     const int any = __syncthreads_or(has);
@@ -293,40 +381,9 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
         if (r >= nr)
             break;
         const uint32_t* gr = g2s + r * WP + PAD;
-        uint32_t* out = d2 + (long long)(r0 + r) * ldo;
-        for (int j = threadIdx.x; j < W; j += blockDim.x) {
-            uint32_t best = gr[j];
-            // d = 1 .. PAD, four per step, no bounds checks (with the frame,
-            // the zero padding supplies the distance to the left and right
-            // frame when it is within PAD columns)
-            int d = 1;
-#pragma unroll
-            for (int step = 0; step < PAD / 4; ++step) {
-                const int d0 = 1 + 4 * step;
-                if ((uint32_t)(d0 * d0) >= best)
-                    break;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint32_t dd = (uint32_t)((d0 + u) * (d0 + u));
-                    best = min(best, __builtin_elementwise_add_sat(dd, gr[j - d0 - u]));
-                    best = min(best, __builtin_elementwise_add_sat(dd, gr[j + d0 + u]));
-                }
-                d = d0 + 4;
-            }
-            // beyond the padding: checked, one column per side at a time
-            if (frame && (uint32_t)d * (uint32_t)d < best) {
-                const uint32_t e = (uint32_t)min(j + 1, W - j);
-                best = min(best, e * e);
-            }
-            for (; (uint32_t)d * (uint32_t)d < best && (j - d >= 0 || j + d < W); ++d) {
-                const uint32_t dd = (uint32_t)d * (uint32_t)d;
-                if (j - d >= 0)
-                    best = min(best, __builtin_elementwise_add_sat(dd, gr[j - d]));
-                if (j + d < W)
-                    best = min(best, __builtin_elementwise_add_sat(dd, gr[j + d]));
-            }
-            out[j] = best;
-        }
+        char* out = reinterpret_cast<char*>(d2 + (long long)(r0 + r) * ldo);
+        for (int j = threadIdx.x; j < W; j += blockDim.x)
+            *reinterpret_cast<uint32_t*>(out + (uint32_t)j * 4u) = row_min(gr, j, W, frame);
     }
 }
 
