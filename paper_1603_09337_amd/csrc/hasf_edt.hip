@@ -330,8 +330,6 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
         g2s[r * WP + (k < PAD ? k : W + k)] = pad;
     }
     int has = 0;
-    // the segment's rows of masks and carries: uniform bases and 32-bit
-    // offsets (loads with a scalar base address)
 #pragma unroll 4
     for (int c = threadIdx.x; c < W; c += blockDim.x) {
         const uint32_t m = mask[(size_t)s * W + c];
