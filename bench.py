@@ -51,6 +51,9 @@ HBM_PEAK = 8.0e12  # bytes/s
 PROFILE_COUNTS = os.path.join(ROOT, "profiles", "filter_512x512_r5_counters.json")
 # exact EDT: 1 byte read + 4 bytes written per pixel
 EDT_BYTES_PER_PX = 5
+# HBM bytes per hasf_edt_sq call on the 4096x4096 input, from rocprofv3 --pmc
+# (FETCH_SIZE, WRITE_SIZE of the EDT kernels of the same calls as bench_edt)
+EDT_COUNTS = os.path.join(ROOT, "profiles", "edt_4096_counters.json")
 
 
 def parse():
@@ -108,8 +111,11 @@ def bench_edt(ctx, reps=20):
     torch.cuda.synchronize()
     t = e0.elapsed_time(e1) / 1e3 / reps
     bytes_ = EDT_BYTES_PER_PX * Hn * Wn
+    traffic = None
+    if os.path.exists(EDT_COUNTS):
+        traffic = json.load(open(EDT_COUNTS)).get("hbm_bytes_per_call")
     return {"bound": "hbm", "achieved": round(bytes_ / t / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-            "frac": round(bytes_ / t / HBM_PEAK, 4), "traffic": None, "us_per_call": round(t * 1e6, 1),
+            "frac": round(bytes_ / t / HBM_PEAK, 4), "traffic": traffic, "us_per_call": round(t * 1e6, 1),
             "workload": "hasf_edt_sq 4096x4096, border is feature (the 4096x4096 r=10 input)",
             "bytes_per_call": bytes_}
 

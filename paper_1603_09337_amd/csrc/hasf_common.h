@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "libhasf.h"
 
 #define HASF_HD __host__ __device__ __forceinline__
@@ -158,6 +160,24 @@ struct ImageLayout {
 };
 
 inline size_t hasf_align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Raises a kernel's dynamic LDS limit to `bytes` on the current device, once
+// per device (bit d of `done` records device d; devices past 63 set it on
+// every call). Launchers run on callers' threads and on server threads.
+inline hipError_t allow_dyn_lds(const void* fn, int bytes, std::atomic<uint64_t>& done)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    const uint64_t bit = dev >= 0 && dev < 64 ? 1ull << dev : 0ull;
+    if (bit && (done.load(std::memory_order_acquire) & bit))
+        return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        done.fetch_or(bit, std::memory_order_acq_rel);
+    return e;
+}
 
 inline int hasf_levels(int r)
 {

@@ -420,23 +420,16 @@ hipError_t launch_edt(const uint8_t* F, int H, int W, long long ld, int frame, i
     // of it, else up to 8 rows of uint16 g
     const size_t lds_dyn = lds_max - 1024;
     const int block = std::min(512, std::max(256, (W + 63) / 64 * 64));
-    static std::atomic<bool> attr{false};
-    if (!attr.load(std::memory_order_acquire)) {
-        hipError_t e = hipFuncSetAttribute((const void*)edt_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds_dyn);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)edt_rows32<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds_dyn);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)edt_rows32<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds_dyn);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)edt_rows32<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds_dyn);
-        if (e != hipSuccess)
-            return e;
-        attr.store(true, std::memory_order_release);
-    }
+    static std::atomic<uint64_t> attr_rows{0}, attr_r4{0}, attr_r2{0}, attr_r1{0};
+    hipError_t e = allow_dyn_lds((const void*)edt_rows, (int)lds_dyn, attr_rows);
+    if (e == hipSuccess)
+        e = allow_dyn_lds((const void*)edt_rows32<4>, (int)lds_dyn, attr_r4);
+    if (e == hipSuccess)
+        e = allow_dyn_lds((const void*)edt_rows32<2>, (int)lds_dyn, attr_r2);
+    if (e == hipSuccess)
+        e = allow_dyn_lds((const void*)edt_rows32<1>, (int)lds_dyn, attr_r1);
+    if (e != hipSuccess)
+        return e;
     const size_t row32 = (size_t)(W + 2 * PAD) * 4;
     if (row32 <= lds_dyn) {
         // two rows per strip and 512 threads: four workgroups share a CU, so

@@ -658,15 +658,10 @@ int filter_block() { return BLOCK; }
 hipError_t launch_filter(const ImgDesc* d_desc, int n, int* d_next, int grid, size_t lds_bytes,
                          hipStream_t stream, unsigned* done)
 {
-    // launched from the caller's thread and from a server's dispatcher thread
-    static std::atomic<bool> attr_set{false};
-    if (!attr_set.load(std::memory_order_acquire)) {
-        hipError_t e = hipFuncSetAttribute((const void*)hasf_filter_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 2048);
-        if (e != hipSuccess)
-            return e;
-        attr_set.store(true, std::memory_order_release);
-    }
+    static std::atomic<uint64_t> attr_done{0};
+    const hipError_t e = allow_dyn_lds((const void*)hasf_filter_kernel, 160 * 1024 - 2048, attr_done);
+    if (e != hipSuccess)
+        return e;
     hipLaunchKernelGGL(hasf_filter_kernel, dim3(grid), dim3(BLOCK), lds_bytes, stream, d_desc, n, d_next, done);
     return hipGetLastError();
 }

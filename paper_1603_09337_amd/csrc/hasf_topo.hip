@@ -215,14 +215,10 @@ namespace hasf_detail {
 
 hipError_t launch_topo(const TopoArgs& a, size_t lds_bytes, hipStream_t stream)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)hasf_topo_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
-        if (e != hipSuccess)
-            return e;
-        attr_set = true;
-    }
+    static std::atomic<uint64_t> attr_done{0};
+    const hipError_t e = allow_dyn_lds((const void*)hasf_topo_kernel, 160 * 1024 - 4096, attr_done);
+    if (e != hipSuccess)
+        return e;
     hipLaunchKernelGGL(hasf_topo_kernel, dim3(1), dim3(BLOCK), lds_bytes, stream, a);
     return hipGetLastError();
 }
