@@ -54,6 +54,9 @@ EDT_BYTES_PER_PX = 5
 # HBM bytes per hasf_edt_sq call on the 4096x4096 input, from rocprofv3 --pmc
 # (FETCH_SIZE, WRITE_SIZE of the EDT kernels of the same calls as bench_edt)
 EDT_COUNTS = os.path.join(ROOT, "profiles", "edt_4096_counters.json")
+# HBM bytes of one whole 4096x4096 r=10 filter on the grid path, from the same
+# rocprofv3 --pmc runs
+LARGE_COUNTS = os.path.join(ROOT, "profiles", "filter_4096x4096_r10_counters.json")
 
 
 def parse():
@@ -140,8 +143,17 @@ def bench_large(ctx, reps=3):
         ctx.sync()
         ts.append(e0.elapsed_time(e1))
     ms = min(ts)
-    return {"workload": "hasf 4096x4096 r=10, C empty, one image (grid of workgroups)", "ms": round(ms, 2),
-            "Mpixel_per_s": round(X.size / ms / 1e3, 2), "frames_per_s": round(1e3 / ms, 3)}
+    out = {"workload": "hasf 4096x4096 r=10, C empty, one image (grid of workgroups)", "ms": round(ms, 2),
+           "Mpixel_per_s": round(X.size / ms / 1e3, 2), "frames_per_s": round(1e3 / ms, 3)}
+    # the thinning and thickening passes against HBM: the measured bytes of the
+    # whole filter over its time (the passes are most of it)
+    if os.path.exists(LARGE_COUNTS):
+        hbm = json.load(open(LARGE_COUNTS)).get("hbm_bytes_per_filter")
+        if hbm:
+            out["hbm"] = {"bound": "hbm", "traffic": hbm, "achieved": round(hbm / (ms / 1e3) / 1e9, 1),
+                          "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                          "frac": round(hbm / (ms / 1e3) / HBM_PEAK, 4)}
+    return out
 
 
 def run_stream(srv, frames, arrivals):
