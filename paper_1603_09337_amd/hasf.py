@@ -114,15 +114,14 @@ def simple_lut(n: int = 8):
     return [(bits[m >> 5] >> (m & 31)) & 1 for m in range(256)]
 
 
-def _image(item, tag=""):
+def _image(item, tag="", device=None):
     """hasf_image for (X, C, r) or (X, C, r, D, conn)."""
     X, C, r = item[0], item[1], item[2]
     D = item[3] if len(item) > 3 else None
     conn = item[4] if len(item) > 4 else 0
-    H, W, ld = _img(X, "X" + tag)
-    for name, T in (("C", C), ("D", D)):
-        if T is not None and (T.shape != X.shape or T.stride(0) != ld):
-            raise ValueError("%s%s must match X's shape and pitch" % (name, tag))
+    H, W, ld = _img(X, "X" + tag, device)
+    _companion(C, X, "C" + tag)
+    _companion(D, X, "D" + tag)
     return _Image(X.data_ptr(), C.data_ptr() if C is not None else None, H, W, ld, r,
                   D.data_ptr() if D is not None else None, conn)
 
@@ -131,10 +130,25 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def _img(t, name):
-    if t.dtype.__repr__() != "torch.uint8" or t.dim() != 2 or t.stride(1) != 1 or not t.is_cuda:
+def _img(t, name, device=None):
+    """(H, W, pitch) of a 2D uint8 CUDA tensor with unit column stride (and,
+    when device is given, on that device)."""
+    if t is None or t.dtype != torch.uint8 or t.dim() != 2 or t.stride(1) != 1 or not t.is_cuda:
         raise ValueError("%s must be a 2D uint8 CUDA tensor with unit column stride" % name)
+    if t.shape[0] > 1 and t.stride(0) < t.shape[1]:
+        raise ValueError("%s: rows overlap (pitch %d < width %d)" % (name, t.stride(0), t.shape[1]))
+    if device is not None and t.device.index != device:
+        raise ValueError("%s is on cuda:%s, the context on cuda:%d" % (name, t.device.index, device))
     return t.shape[0], t.shape[1], t.stride(0)
+
+
+def _companion(T, X, name):
+    """A plane that shares X's layout (C, D, K, V): same dtype, device, shape and pitch."""
+    if T is None:
+        return
+    _img(T, name, X.device.index)
+    if T.shape != X.shape or T.stride(0) != X.stride(0):
+        raise ValueError("%s must match X's shape and pitch" % name)
 
 
 class Context:
@@ -173,36 +187,40 @@ class Context:
         self._check(_lib.hasf_sync(self._h))
 
     def edt_sq(self, feat, border_is_feature: bool = False, out=None):
-        H, W, ld = _img(feat, "feat")
+        H, W, ld = _img(feat, "feat", self.device)
         if out is None:
             out = self._torch.empty((H, W), dtype=self._torch.int32, device=feat.device)
+        elif (out.dtype not in (torch.int32, torch.uint32) or out.dim() != 2 or tuple(out.shape) != (H, W)
+              or out.stride(1) != 1 or not out.is_cuda or out.device.index != self.device
+              or (H > 1 and out.stride(0) < W)):
+            raise ValueError("out must be an (H, W) int32 or uint32 tensor with unit column stride on cuda:%d"
+                             % self.device)
         self._stream()
         self._check(_lib.hasf_edt_sq(self._h, _ptr(feat), H, W, ld, int(bool(border_is_feature)), _ptr(out),
                                      out.stride(0)))
         return out
 
     def homotopic_thin(self, X, K=None):
-        H, W, ld = _img(X, "X")
-        if K is not None and (K.shape != X.shape or K.stride(0) != ld):
-            raise ValueError("K must match X's shape and pitch")
+        H, W, ld = _img(X, "X", self.device)
+        _companion(K, X, "K")
         self._stream()
         self._check(_lib.hasf_homotopic_thin(self._h, _ptr(X), _ptr(K), H, W, ld))
         return X
 
     def homotopic_thicken(self, Y, V):
-        H, W, ld = _img(Y, "Y")
-        if V is None or V.shape != Y.shape or V.stride(0) != ld:
-            raise ValueError("V must match Y's shape and pitch")
+        H, W, ld = _img(Y, "Y", self.device)
+        if V is None:
+            raise ValueError("V must not be None")
+        _companion(V, Y, "V")
         self._stream()
         self._check(_lib.hasf_homotopic_thicken(self._h, _ptr(Y), _ptr(V), H, W, ld))
         return Y
 
     def filter(self, X, C=None, r: int = 1, D=None, conn: int = 8):
         """hasf_filter (D None and conn 8) or hasf_filter_cd."""
-        H, W, ld = _img(X, "X")
-        for name, T in (("C", C), ("D", D)):
-            if T is not None and (T.shape != X.shape or T.stride(0) != ld):
-                raise ValueError("%s must match X's shape and pitch" % name)
+        H, W, ld = _img(X, "X", self.device)
+        _companion(C, X, "C")
+        _companion(D, X, "D")
         self._stream()
         if D is None and conn == 8:
             self._check(_lib.hasf_filter(self._h, _ptr(X), _ptr(C), H, W, ld, r))
@@ -215,7 +233,7 @@ class Context:
         items: (X, C or None, r) or (X, C or None, r, D or None, conn)."""
         arr = (_Image * max(1, len(items)))()
         for k, it in enumerate(items):
-            arr[k] = _image(it, "[%d]" % k)
+            arr[k] = _image(it, "[%d]" % k, self.device)
         return (arr, len(items), list(items))
 
     def run_plan(self, plan):
@@ -227,7 +245,7 @@ class Context:
         """items: sequence of (X, C or None, r) or (X, C or None, r, D or None, conn)."""
         arr = (_Image * max(1, len(items)))()
         for k, it in enumerate(items):
-            arr[k] = _image(it, "[%d]" % k)
+            arr[k] = _image(it, "[%d]" % k, self.device)
         self._stream()
         self._check(_lib.hasf_filter_batch(self._h, arr, len(items)))
         return [it[0] for it in items]
@@ -251,7 +269,7 @@ class Server:
 
     def submit(self, X, C=None, r: int = 1, check: bool = True, D=None, conn: int = 0):
         """Queue a frame; returns its ticket (or the status when check=False and it fails)."""
-        im = _image((X, C, r, D, conn))
+        im = _image((X, C, r, D, conn), device=self._ctx.device)
         t = ctypes.c_uint64()
         st = _lib.hasf_serve_submit(self._h, ctypes.byref(im), ctypes.byref(t))
         if st != HASF_OK:

@@ -74,3 +74,15 @@ def test_serve_rejects_null_arguments():
     assert lib.hasf_serve_wait(None, 1, 0, None) == hasf.HASF_EINVAL
     assert lib.hasf_serve_stats(None, None) == hasf.HASF_EINVAL
     assert lib.hasf_serve_stop(None) == hasf.HASF_EINVAL
+
+
+def test_binding_refuses_host_and_malformed_tensors():
+    # checked before any device work, so this runs without a GPU
+    import torch
+    from paper_1603_09337_amd import hasf
+    for t in (torch.zeros((4, 4), dtype=torch.uint8), torch.zeros((4, 4), dtype=torch.float32),
+              torch.zeros((4, 4, 2), dtype=torch.uint8), None):
+        with pytest.raises(ValueError):
+            hasf._img(t, "X")
+    with pytest.raises(ValueError):
+        hasf._image((torch.zeros((4, 4), dtype=torch.uint8), None, 1))
