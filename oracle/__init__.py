@@ -64,6 +64,8 @@ def _load():
     lib.oracle_hf.restype = ctypes.c_long
     lib.oracle_hasf.argtypes = [U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int, U8P]
     lib.oracle_hasf_cd.argtypes = [U8P, U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, U8P]
+    lib.oracle_hasf_order.argtypes = [U8P, U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, U8P]
     lib.oracle_hasf.restype = ctypes.c_long
     lib.oracle_hasf_queue.argtypes = [U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.oracle_hasf_queue.restype = ctypes.c_long
@@ -173,10 +175,12 @@ def hf(X, i: int) -> np.ndarray:
     return x
 
 
-def hasf(X, C, r: int, stages: bool = False, queue: bool = False, D=None, n: int = 8):
+def hasf(X, C, r: int, stages: bool = False, queue: bool = False, D=None, n: int = 8, order: int = 0):
     """HASF of order r (Sec. 2) with constraint sets C (kept object) and D (kept
-    background), for the connectivity pair (n, n-bar) = (8, 4) or (4, 8); with
-    stages=True also returns an (r, 4, H, W) stage dump."""
+    background), for the connectivity pair (n, n-bar) = (8, 4) or (4, 8);
+    order 0 applies HF_i o HC_i at every radius (the formula: cutting first),
+    order 1 the dual HC_i o HF_i (filling first). With stages=True also
+    returns an (r, 4, H, W) dump of the states in the order produced."""
     x = np.ascontiguousarray(X, dtype=np.uint8).copy()
     c, cp = _opt_u8(C)
     H, W = x.shape
@@ -186,7 +190,11 @@ def hasf(X, C, r: int, stages: bool = False, queue: bool = False, D=None, n: int
         return x
     st = np.zeros((max(r, 1), 4, H, W), dtype=np.uint8) if stages else None
     sp = st.ctypes.data_as(U8P) if st is not None else None
-    if D is None and n == 8:
+    if order != 0:
+        assert not queue
+        d, dp = _opt_u8(D)
+        _check(_load().oracle_hasf_order(x.ctypes.data_as(U8P), cp, dp, H, W, r, n, order, sp), "hasf_order")
+    elif D is None and n == 8:
         _check(_load().oracle_hasf(x.ctypes.data_as(U8P), cp, H, W, r, sp), "hasf")
     else:
         d, dp = _opt_u8(D)

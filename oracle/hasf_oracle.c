@@ -626,10 +626,12 @@ long oracle_hf(uint8_t* X, int H, int W, int i)
     return rc < 0 ? rc : 0;
 }
 
-static long hasf_core(uint8_t* X, const uint8_t* C, const uint8_t* D, int H, int W, int r, int n,
+/* order 0: HF_i o HC_i at every radius (the formula of Sec. 2, cutting
+ * first); order 1: the dual sequence HC_i o HF_i (filling first). */
+static long hasf_core(uint8_t* X, const uint8_t* C, const uint8_t* D, int H, int W, int r, int n, int order,
                       uint8_t* stages, sched_fn run)
 {
-    if (H < 1 || W < 1 || r < 0 || (n != 8 && n != 4))
+    if (H < 1 || W < 1 || r < 0 || (n != 8 && n != 4) || (order != 0 && order != 1))
         return ORACLE_EINVAL;
     const size_t N = (size_t)H * W;
     normalise(X, N);
@@ -657,9 +659,15 @@ static long hasf_core(uint8_t* X, const uint8_t* C, const uint8_t* D, int H, int
     w.lut = lut_for(n);
     for (int i = 1; i <= r && rc == 0; ++i) {
         uint8_t* st = stages ? stages + (size_t)(i - 1) * 4 * N : NULL;
-        rc = hc(X, C ? Cn : NULL, H, W, i, &w, st);
-        if (rc == 0)
-            rc = hf(X, D ? Dn : NULL, H, W, i, &w, st ? st + 2 * N : NULL);
+        if (order == 0) {
+            rc = hc(X, C ? Cn : NULL, H, W, i, &w, st);
+            if (rc == 0)
+                rc = hf(X, D ? Dn : NULL, H, W, i, &w, st ? st + 2 * N : NULL);
+        } else {
+            rc = hf(X, D ? Dn : NULL, H, W, i, &w, st);
+            if (rc == 0)
+                rc = hc(X, C ? Cn : NULL, H, W, i, &w, st ? st + 2 * N : NULL);
+        }
     }
     work_free(&w);
     free(Cn); free(Dn);
@@ -672,7 +680,7 @@ static long hasf_core(uint8_t* X, const uint8_t* C, const uint8_t* D, int H, int
  * and after the filling. */
 long oracle_hasf(uint8_t* X, const uint8_t* C, int H, int W, int r, uint8_t* stages)
 {
-    return hasf_core(X, C, NULL, H, W, r, 8, stages, sched_subfield);
+    return hasf_core(X, C, NULL, H, W, r, 8, 0, stages, sched_subfield);
 }
 
 /* HASF^{C,D} of order r for the connectivity pair (n, n-bar), n = 8: (8,4),
@@ -680,13 +688,22 @@ long oracle_hasf(uint8_t* X, const uint8_t* C, int H, int W, int r, uint8_t* sta
  * adds a point of D (D <- D \ X), so D stays background. NULL = empty. */
 long oracle_hasf_cd(uint8_t* X, const uint8_t* C, const uint8_t* D, int H, int W, int r, int n, uint8_t* stages)
 {
-    return hasf_core(X, C, D, H, W, r, n, stages, sched_subfield);
+    return hasf_core(X, C, D, H, W, r, n, 0, stages, sched_subfield);
+}
+
+/* As oracle_hasf_cd, in the given order: 0 = HF_i o HC_i at every radius (the
+ * formula), 1 = the dual HC_i o HF_i (filling first). stages then holds, per
+ * radius, the four states in the order they are produced. */
+long oracle_hasf_order(uint8_t* X, const uint8_t* C, const uint8_t* D, int H, int W, int r, int n, int order,
+                       uint8_t* stages)
+{
+    return hasf_core(X, C, D, H, W, r, n, order, stages, sched_subfield);
 }
 
 /* The same filter with the queue-ordered schedule below. */
 long oracle_hasf_queue(uint8_t* X, const uint8_t* C, int H, int W, int r)
 {
-    return hasf_core(X, C, NULL, H, W, r, 8, NULL, queue_schedule);
+    return hasf_core(X, C, NULL, H, W, r, 8, 0, NULL, queue_schedule);
 }
 
 /* ------------------------------------------------------------------------ */
