@@ -161,7 +161,14 @@ hasf_status hasf_filter(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, int H, int 
 hasf_status hasf_filter_cd(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, const uint8_t* D, int H, int W,
                            int64_t ld, int r, int conn);
 
-/* One image of a batch (zero-initialise: D = NULL and conn = 0 give hasf_filter). */
+/*
+ * One image of a batch (zero-initialise: D = NULL, conn = 0 and order = 0
+ * give hasf_filter). order selects the sequence at every radius: 0 applies
+ * HF_i o HC_i (the formula of Sec. 2, cutting first), 1 the dual HC_i o HF_i
+ * (filling first); HASF_EINVAL for other values. A batch of one image is
+ * hasf_filter on it, so hasf_filter_batch(ctx, &img, 1) filters one image in
+ * the dual order.
+ */
 typedef struct {
     uint8_t* X;        /* device, in/out */
     const uint8_t* C;  /* device or NULL */
@@ -170,6 +177,7 @@ typedef struct {
     int r;
     const uint8_t* D;  /* device or NULL: background constraint set, as in hasf_filter_cd */
     int conn;          /* 0 or 8: (8,4); 4: (4,8) */
+    int order;         /* 0: cutting first (HF_i o HC_i); 1: filling first (HC_i o HF_i) */
 } hasf_image;
 
 /*

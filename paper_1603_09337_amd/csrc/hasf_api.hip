@@ -343,6 +343,11 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
                     imgs[k].conn);
             return HASF_EINVAL;
         }
+        if (imgs[k].order != 0 && imgs[k].order != 1) {
+            set_err(ctx, "%s: image %d: order = %d (0: cutting first; 1: filling first)", what, k,
+                    imgs[k].order);
+            return HASF_EINVAL;
+        }
     }
     if (n == 0)
         return HASF_OK;
@@ -386,7 +391,7 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
         d.lds = L.lds ? 1 : 0;
         d.D = im.D;
         d.conn4 = im.conn == 4 ? 1 : 0;
-        d.pad_ = 0;
+        d.order = im.order;
         // offsets for now; rebased after allocation
         d.gplanes = (uint64_t*)bytes;
         bytes += L.planes_bytes;
@@ -497,6 +502,7 @@ hasf_status hasf_filter_cd(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, const ui
     im.r = r;
     im.D = D;
     im.conn = conn;
+    im.order = 0;
     return run_images(ctx, &im, 1, "hasf_filter");
 }
 

@@ -133,7 +133,7 @@ struct ImgDesc {
     uint64_t* ent_msk;  // level entries: candidate bits
     const uint8_t* D;   // background constraint set (same pitch as X) or NULL
     int conn4;          // 1: the (4,8) connectivity pair; 0: (8,4)
-    int pad_;
+    int order;          // 0: HF_i o HC_i at every radius (cutting first); 1: HC_i o HF_i
 };
 
 // Control block of one image filtered by a grid of workgroups (device memory,

@@ -263,11 +263,15 @@ __device__ __attribute__((noinline)) void run_image(const ImgDesc* __restrict__ 
     rows_to_sub(g, threadIdx.x, BLOCK);
     __syncthreads();
     const int r = dp->r;
+    // phases in the order of the enum (HC_i then HF_i), or rotated by two for
+    // the dual order (HF_i then HC_i); each operator saves its own input in A
+    const int rot = dp->order ? 2 : 0;
     for (int i = 1; i <= r; ++i) {
         const int nlev = levels_at(i);
         // HC_i (eq. i): thin, then thicken; HF_i (eq. ii): thicken, then thin
-        for (int ph = 0; ph < 4; ++ph) {
-            if (i > 1 || ph > 0) {
+        for (int k = 0; k < 4; ++k) {
+            const int ph = (k + rot) & 3;
+            if (i > 1 || k > 0) {
                 sub_to_rows(g, threadIdx.x, BLOCK);
                 __syncthreads();
             }
@@ -557,10 +561,12 @@ __device__ __forceinline__ bool run_image_grid(const ImgDesc* __restrict__ dp, G
     if (!grid_sync(gs, s_ok))
         return false;
     const int r = dp->r;
+    const int rot = dp->order ? 2 : 0;  // as in run_image
     for (int i = 1; i <= r; ++i) {
         const int nlev = levels_at(i);
-        for (int ph = 0; ph < 4; ++ph) {
-            if (i > 1 || ph > 0) {
+        for (int k = 0; k < 4; ++k) {
+            const int ph = (k + rot) & 3;
+            if (i > 1 || k > 0) {
                 sub_to_rows(g, t0, tn);
                 if (!grid_sync(gs, s_ok))
                     return false;

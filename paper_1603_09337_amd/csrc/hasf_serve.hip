@@ -189,7 +189,7 @@ void fill_desc(hasf_server* s, const Frame* f, ImgDesc& d)
     d.lds = f->lay.lds ? 1 : 0;
     d.D = f->img.D;
     d.conn4 = f->img.conn == 4 ? 1 : 0;
-    d.pad_ = 0;
+    d.order = f->img.order;
     char* base = s->pool_mem + f->off;
     d.gplanes = (uint64_t*)base;
     d.ent_idx = (uint32_t*)(base + f->lay.planes_bytes);
@@ -465,7 +465,8 @@ hasf_status hasf_serve_submit(hasf_server* s, const hasf_image* img, uint64_t* t
     if (!s || !img || !ticket)
         return HASF_EINVAL;
     if (!img->X || img->H < 1 || img->W < 1 || (int64_t)img->H + img->W > 65535 || img->ld < img->W ||
-        img->r < 0 || img->r > HASF_R_MAX || (img->conn != 0 && img->conn != 4 && img->conn != 8)) {
+        img->r < 0 || img->r > HASF_R_MAX || (img->conn != 0 && img->conn != 4 && img->conn != 8) ||
+        (img->order != 0 && img->order != 1)) {
         std::lock_guard<std::mutex> g(s->mu);
         ++s->rejected;
         return HASF_EINVAL;

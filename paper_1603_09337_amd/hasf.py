@@ -41,7 +41,8 @@ class _Opts(ctypes.Structure):
 
 class _Image(ctypes.Structure):
     _fields_ = [("X", ctypes.c_void_p), ("C", ctypes.c_void_p), ("H", ctypes.c_int), ("W", ctypes.c_int),
-                ("ld", ctypes.c_int64), ("r", ctypes.c_int), ("D", ctypes.c_void_p), ("conn", ctypes.c_int)]
+                ("ld", ctypes.c_int64), ("r", ctypes.c_int), ("D", ctypes.c_void_p), ("conn", ctypes.c_int),
+                ("order", ctypes.c_int)]
 
 
 class _ServeOpts(ctypes.Structure):
@@ -115,15 +116,16 @@ def simple_lut(n: int = 8):
 
 
 def _image(item, tag="", device=None):
-    """hasf_image for (X, C, r) or (X, C, r, D, conn)."""
+    """hasf_image for (X, C, r), (X, C, r, D, conn) or (X, C, r, D, conn, order)."""
     X, C, r = item[0], item[1], item[2]
     D = item[3] if len(item) > 3 else None
     conn = item[4] if len(item) > 4 else 0
+    order = item[5] if len(item) > 5 else 0
     H, W, ld = _img(X, "X" + tag, device)
     _companion(C, X, "C" + tag)
     _companion(D, X, "D" + tag)
     return _Image(X.data_ptr(), C.data_ptr() if C is not None else None, H, W, ld, r,
-                  D.data_ptr() if D is not None else None, conn)
+                  D.data_ptr() if D is not None else None, conn, order)
 
 
 def _ptr(t):
@@ -216,8 +218,12 @@ class Context:
         self._check(_lib.hasf_homotopic_thicken(self._h, _ptr(Y), _ptr(V), H, W, ld))
         return Y
 
-    def filter(self, X, C=None, r: int = 1, D=None, conn: int = 8):
-        """hasf_filter (D None and conn 8) or hasf_filter_cd."""
+    def filter(self, X, C=None, r: int = 1, D=None, conn: int = 8, order: int = 0):
+        """hasf_filter (D None, conn 8, order 0), hasf_filter_cd (order 0) or,
+        for the dual order (filling first), hasf_filter_batch of this one image."""
+        if order != 0:
+            self.filter_batch([(X, C, r, D, conn, order)])
+            return X
         H, W, ld = _img(X, "X", self.device)
         _companion(C, X, "C")
         _companion(D, X, "D")
@@ -230,7 +236,8 @@ class Context:
 
     def plan_batch(self, items):
         """Prepare the descriptor array of a batch once (the tensors must stay alive).
-        items: (X, C or None, r) or (X, C or None, r, D or None, conn)."""
+        items: (X, C or None, r), (X, C or None, r, D or None, conn) or
+        (X, C or None, r, D or None, conn, order)."""
         arr = (_Image * max(1, len(items)))()
         for k, it in enumerate(items):
             arr[k] = _image(it, "[%d]" % k, self.device)
@@ -242,7 +249,8 @@ class Context:
         self._check(_lib.hasf_filter_batch(self._h, arr, n))
 
     def filter_batch(self, items):
-        """items: sequence of (X, C or None, r) or (X, C or None, r, D or None, conn)."""
+        """items: sequence of (X, C or None, r), (X, C or None, r, D or None, conn)
+        or (X, C or None, r, D or None, conn, order)."""
         arr = (_Image * max(1, len(items)))()
         for k, it in enumerate(items):
             arr[k] = _image(it, "[%d]" % k, self.device)
@@ -267,9 +275,9 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit(self, X, C=None, r: int = 1, check: bool = True, D=None, conn: int = 0):
+    def submit(self, X, C=None, r: int = 1, check: bool = True, D=None, conn: int = 0, order: int = 0):
         """Queue a frame; returns its ticket (or the status when check=False and it fails)."""
-        im = _image((X, C, r, D, conn), device=self._ctx.device)
+        im = _image((X, C, r, D, conn, order), device=self._ctx.device)
         t = ctypes.c_uint64()
         st = _lib.hasf_serve_submit(self._h, ctypes.byref(im), ctypes.byref(t))
         if st != HASF_OK:
@@ -279,9 +287,9 @@ class Server:
         self._keep[t.value] = (X, C, D)
         return t.value
 
-    def submit_raw(self, ptr, H, W, ld, r, cptr=None, dptr=None, conn=0):
+    def submit_raw(self, ptr, H, W, ld, r, cptr=None, dptr=None, conn=0, order=0):
         """Queue a frame given by device pointer (the caller keeps it alive); returns (status, ticket)."""
-        im = _Image(ptr, cptr, H, W, ld, r, dptr, conn)
+        im = _Image(ptr, cptr, H, W, ld, r, dptr, conn, order)
         t = ctypes.c_uint64()
         st = _lib.hasf_serve_submit(self._h, ctypes.byref(im), ctypes.byref(t))
         return st, t.value
