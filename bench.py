@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--plain", type=int, default=64)
     ap.add_argument("--cpu-sample", type=int, default=12)
     ap.add_argument("--serve-seconds", type=float, default=4.0)
-    ap.add_argument("--mixed-seconds", type=float, default=1.0)
+    ap.add_argument("--mixed-seconds", type=float, default=10.0)
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--lanes", type=int, default=4)
     ap.add_argument("--no-serve", action="store_true")
