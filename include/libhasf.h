@@ -80,7 +80,10 @@ hasf_status hasf_create(const hasf_opts* opts, hasf_ctx** out);
 void hasf_destroy(hasf_ctx* ctx);
 
 /* Use `hip_stream` (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream)
- * for every later call on ctx. NULL selects the null stream. */
+ * for every later call on ctx. NULL selects the null stream. The context's
+ * calls stay in order across a change: the new stream first waits for the
+ * work already queued on the previous one (they share the context's scratch
+ * memory). Setting the current stream again does nothing. */
 hasf_status hasf_set_stream(hasf_ctx* ctx, void* hip_stream);
 
 /* Wait for ctx's stream; returns HASF_EDEVICE if queued device work failed, and

@@ -90,6 +90,33 @@ hasf_status ensure_scratch(hasf_ctx* ctx, size_t bytes)
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+// Pinned host staging for the descriptors a call uploads, at least `bytes`
+// long. It is reused once the previous call's upload has been consumed (its
+// event), so a call does not wait for the device work queued before it.
+hasf_status stage_buffer(hasf_ctx* ctx, size_t bytes, char** out)
+{
+    hipError_t e = ctx->ev_stage ? hipEventSynchronize(ctx->ev_stage)
+                                 : hipEventCreateWithFlags(&ctx->ev_stage, hipEventDisableTiming);
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "descriptor staging");
+    if (bytes > ctx->h_stage_bytes) {
+        if (ctx->h_stage)
+            hipHostFree(ctx->h_stage);
+        ctx->h_stage = nullptr;
+        ctx->h_stage_bytes = 0;
+        const size_t want = std::max(bytes, (size_t)1 << 16);
+        e = hipHostMalloc((void**)&ctx->h_stage, want, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->h_stage = nullptr;
+            return dev_fail(ctx, e, "hipHostMalloc(descriptor staging)");
+        }
+        ctx->h_stage_bytes = want;
+    }
+    *out = ctx->h_stage;
+    return HASF_OK;
+}
+
 int levels_host(int r)
 {
     int c = 0;
@@ -211,6 +238,10 @@ hasf_status hasf_create(const hasf_opts* opts, hasf_ctx** out)
     c->grid_pending = false;
     c->side = nullptr;
     c->ev_fork = c->ev_join = nullptr;
+    c->ev_switch = nullptr;
+    c->h_stage = nullptr;
+    c->h_stage_bytes = 0;
+    c->ev_stage = nullptr;
     e = hipMalloc((void**)&c->d_grid_err, 256);
     if (e == hipSuccess)
         e = hipMemset(c->d_grid_err, 0, 256);
@@ -245,6 +276,12 @@ void hasf_destroy(hasf_ctx* ctx)
         hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join)
         hipEventDestroy(ctx->ev_join);
+    if (ctx->ev_switch)
+        hipEventDestroy(ctx->ev_switch);
+    if (ctx->ev_stage)
+        hipEventDestroy(ctx->ev_stage);
+    if (ctx->h_stage)
+        hipHostFree(ctx->h_stage);
     delete ctx;
 }
 
@@ -254,7 +291,22 @@ hasf_status hasf_set_stream(hasf_ctx* ctx, void* hip_stream)
         set_err(nullptr, "hasf_set_stream: ctx is NULL");
         return HASF_EINVAL;
     }
-    ctx->stream = (hipStream_t)hip_stream;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    if (s == ctx->stream)
+        return HASF_OK;
+    // every call of a context uses its one scratch buffer: the new stream
+    // waits for the work already queued on the old one, so calls never overlap
+    hipSetDevice(ctx->device);
+    hipError_t e = hipSuccess;
+    if (!ctx->ev_switch)
+        e = hipEventCreateWithFlags(&ctx->ev_switch, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev_switch, ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamWaitEvent(s, ctx->ev_switch, 0);
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "hasf_set_stream");
+    ctx->stream = s;
     return HASF_OK;
 }
 
@@ -415,18 +467,20 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
         d.ent_msk = (uint64_t*)(base + meta_bytes + (size_t)d.ent_msk);
     }
     // the counter and every GridCtl start at 0
-    std::vector<char> host(meta_bytes, 0);
-    std::memcpy(host.data() + 256, desc.data(), sizeof(ImgDesc) * (size_t)ns);
+    char* host = nullptr;
+    if ((s = stage_buffer(ctx, meta_bytes, &host)))
+        return s;
+    std::memset(host, 0, meta_bytes);
+    std::memcpy(host + 256, desc.data(), sizeof(ImgDesc) * (size_t)ns);
     for (int q = 0; q < nb; ++q)
-        std::memcpy(host.data() + desc_bytes + gmeta * q + align256(sizeof(GridCtl)), &desc[ns + q],
-                    sizeof(ImgDesc));
-    hipError_t e = hipMemcpyAsync(base, host.data(), meta_bytes, hipMemcpyHostToDevice, ctx->stream);
+        std::memcpy(host + desc_bytes + gmeta * q + align256(sizeof(GridCtl)), &desc[ns + q], sizeof(ImgDesc));
+    // stream-ordered after the previous call's kernels, which read the same
+    // device region; the staging buffer is free again once the event passes
+    hipError_t e = hipMemcpyAsync(base, host, meta_bytes, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev_stage, ctx->stream);
     if (e != hipSuccess)
         return dev_fail(ctx, e, "hipMemcpyAsync(descriptors)");
-    // the pageable source must stay alive until the copy has consumed it
-    e = hipStreamSynchronize(ctx->stream);
-    if (e != hipSuccess)
-        return dev_fail(ctx, e, "hipStreamSynchronize(descriptors)");
     // Grid images: alone, on the context's stream; beside a batch, on the side
     // stream, launched first so that their workgroups are resident while the
     // batch's persistent workgroups take the rest of the device; the
@@ -436,13 +490,17 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
         // created on first use: a process has few hardware queues, and
         // streams beyond them share one and run one after the other
         if (!ctx->side) {
-            e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
-            if (e == hipSuccess)
+            // the events first: ctx->side is set only when all three exist
+            hipStream_t side = nullptr;
+            if (!ctx->ev_fork)
                 e = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
-            if (e == hipSuccess)
+            if (e == hipSuccess && !ctx->ev_join)
                 e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
+            if (e == hipSuccess)
+                e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
             if (e != hipSuccess)
                 return dev_fail(ctx, e, "hasf_filter_batch: side stream");
+            ctx->side = side;
         }
         gs = ctx->side;
         e = hipEventRecord(ctx->ev_fork, ctx->stream);

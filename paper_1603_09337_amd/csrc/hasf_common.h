@@ -244,6 +244,12 @@ struct hasf_ctx {
     // grid images of a batch run on this stream, beside the batch launch
     hipStream_t side;
     hipEvent_t ev_fork, ev_join;
+    // orders a new stream after the old one in hasf_set_stream
+    hipEvent_t ev_switch;
+    // pinned staging of a call's descriptors; ev_stage: its last upload
+    char* h_stage;
+    size_t h_stage_bytes;
+    hipEvent_t ev_stage;
 };
 
 // Workgroups of the grid that filters one image of nwd 64-bit words: at
