@@ -308,7 +308,7 @@ def bench_served(ctx, a, src, Cd):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported (use --gpus 1)" % a.gpus,
+        print("bench.py: libhasf runs on one GPU; --gpus %d is not supported (use --gpus 1)" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
