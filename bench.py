@@ -390,7 +390,7 @@ def main():
             traffic = counts["hbm_bytes_per_image"] * B
         roof = {"bound": "alu", "achieved": round(ach, 3), "peak": round(peak, 3), "unit": "TFLOP/s",
                 "frac": round(ach / peak, 4), "traffic": traffic,
-                "kernel": "hasf_filter_kernel", "ops": "int32 VALU lane-ops"}
+                "kernel": "hasf_filter_kernel<512>", "ops": "int32 VALU lane-ops"}
 
     log("edt 4096x4096")
     edt = bench_edt(ctx)

@@ -9,14 +9,14 @@
 #include "hasf_common.h"
 
 namespace hasf_detail {
-hipError_t launch_filter(const ImgDesc* d_desc, int n, int* d_next, int grid, size_t lds_bytes,
+hipError_t launch_filter(const ImgDesc* d_desc, int n, int* d_next, int grid, int block, size_t lds_bytes,
                          hipStream_t stream, unsigned* done);
-int filter_block();
+int filter_block_for(int n, int num_cu);
 size_t edt_scratch_bytes(int H, int W);
 hipError_t launch_edt(const uint8_t* F, int H, int W, long long ld, int frame, int invert, uint32_t* d2,
                       long long ldo, void* scratch, size_t lds_max, int nxcd, hipStream_t stream);
 hipError_t launch_topo(const TopoArgs& a, size_t lds_bytes, hipStream_t stream);
-int filter_occupancy(size_t lds_bytes);
+int filter_occupancy(size_t lds_bytes, int block);
 hipError_t launch_grid(const ImgDesc* d_desc, GridCtl* d_ctl, unsigned* d_err, int grid, hipStream_t stream);
 int grid_occupancy();
 }  // namespace hasf_detail
@@ -525,9 +525,11 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
             return dev_fail(ctx, e, "hasf_filter_batch: join");
     }
     if (ns > 0) {
-        const int occ = std::max(1, filter_occupancy(lds_need));
+        const int block = filter_block_for(ns, ctx->num_cu);
+        const int occ = std::max(1, filter_occupancy(lds_need, block));
         const int grid = std::min(ns, ctx->num_cu * occ);
-        e = launch_filter((const ImgDesc*)(base + 256), ns, (int*)base, grid, lds_need, ctx->stream, nullptr);
+        e = launch_filter((const ImgDesc*)(base + 256), ns, (int*)base, grid, block, lds_need, ctx->stream,
+                          nullptr);
         if (e != hipSuccess)
             return dev_fail(ctx, e, "hasf_filter launch");
     }

@@ -474,7 +474,8 @@ __device__ __forceinline__ bool test_word(const PassPtrs<LDS>& p, int idx, int r
 // the other three, so flags need no atomics. A pass first collects its
 // flagged live words into a list (4 flags per thread per load), then tests
 // the list densely; a pass whose sub-image has no flagged word is skipped.
-template <bool LDS>
+// NT: the workgroup size (threads) the caller is launched with.
+template <bool LDS, int NT = BLOCK>
 __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& sc)
 {
     const int WW = g.WW;
@@ -502,9 +503,9 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
             lds_i32* cnt = lcnt + (sc.npass & 1);
             // collect: flagged words whose activated candidates are still live;
             // every lane runs the same number of iterations (wave-wide prefix)
-            const int niter = (nw + 4 * BLOCK - 1) / (4 * BLOCK);
+            const int niter = (nw + 4 * NT - 1) / (4 * NT);
             for (int it = 0; it < niter; ++it) {
-                const int b0 = 4 * threadIdx.x + it * 4 * BLOCK;
+                const int b0 = 4 * threadIdx.x + it * 4 * NT;
                 unsigned f4 = 0;
                 if (b0 < nw)
                     f4 = *(const typename std::conditional<LDS, lds_u32*, glb_u32*>::type)(Ds + b0);
@@ -545,7 +546,7 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
             // test the listed words
             const PassPtrs<LDS> pp = pass_ptrs(g, si, sj);
             bool changed_here = false;
-            for (int t = threadIdx.x; t < n; t += BLOCK) {
+            for (int t = threadIdx.x; t < n; t += NT) {
                 const int idx = (int)g.L[t];
                 int rr = (int)((float)idx * invWW);
                 if (rr * WW > idx)

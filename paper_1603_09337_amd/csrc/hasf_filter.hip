@@ -27,6 +27,9 @@
 
 using namespace hasf_dev;
 
+// hasf_filter_kernel is built for BLOCK (512) and for this many threads
+constexpr int FILTER_BLOCK_MAX = 1024;
+
 namespace {
 
 // Feature word at (row, w) for the distance map of this stage.
@@ -214,7 +217,7 @@ __device__ __forceinline__ void run_stage(const ImgDesc* dp, uint64_t* smem, int
 // Levels in increasing order; inside a level, rounds of the four subfield
 // passes until a round changes nothing (the schedule of thinning H and
 // thickening *H, Sec. 2).
-template <bool LDS>
+template <bool LDS, int NT>
 __device__ __attribute__((noinline)) void level_loop(const ImgDesc* __restrict__ dp, uint64_t* smem, bool thin,
                                                      int nlev, lds_u32* cnt, lds_i32* ctl)
 {
@@ -228,12 +231,12 @@ __device__ __attribute__((noinline)) void level_loop(const ImgDesc* __restrict__
             continue;
         const int ser = ++sc.serial;
         const size_t e0 = (size_t)k * g.NWD;
-        for (unsigned t = threadIdx.x; t < c; t += BLOCK) {
+        for (unsigned t = threadIdx.x; t < c; t += NT) {
             const uint32_t p = g.eidx[e0 + t];
             activate_row_word(g, (int)(p >> 10), (int)(p & 1023u), (uint64_t)g.emsk[e0 + t], ser);
         }
         __syncthreads();
-        run_rounds(g, thin, sc);
+        run_rounds<LDS, NT>(g, thin, sc);
     }
     __syncthreads();
 }
@@ -249,18 +252,18 @@ __device__ int levels_at(int i)
     return tab[i];
 }
 
-template <bool LDS>
+template <bool LDS, int NT>
 __device__ __attribute__((noinline)) void run_image(const ImgDesc* __restrict__ dp, uint64_t* smem, lds_u32* cnt,
                                                     lds_i32* ctl)
 {
     const Img<LDS> g = make_img<LDS>(dp, smem, ctl);
-    pack_rows(dp->X, dp->C, dp->ld, g.H, g.W, g.R, g.hasK ? g.K : nullptr, threadIdx.x, BLOCK);
+    pack_rows(dp->X, dp->C, dp->ld, g.H, g.W, g.R, g.hasK ? g.K : nullptr, threadIdx.x, NT);
     if (g.hasD)
-        pack_background(dp->D, dp->ld, g.H, g.W, g.R, g.Dp, threadIdx.x, BLOCK);
-    for (int k = threadIdx.x; k < HASF_LEVELS_MAX; k += BLOCK)
+        pack_background(dp->D, dp->ld, g.H, g.W, g.R, g.Dp, threadIdx.x, NT);
+    for (int k = threadIdx.x; k < HASF_LEVELS_MAX; k += NT)
         cnt[k] = 0;
     __syncthreads();
-    rows_to_sub(g, threadIdx.x, BLOCK);
+    rows_to_sub(g, threadIdx.x, NT);
     __syncthreads();
     const int r = dp->r;
     // phases in the order of the enum (HC_i then HF_i), or rotated by two for
@@ -272,24 +275,24 @@ __device__ __attribute__((noinline)) void run_image(const ImgDesc* __restrict__ 
         for (int k = 0; k < 4; ++k) {
             const int ph = (k + rot) & 3;
             if (i > 1 || k > 0) {
-                sub_to_rows(g, threadIdx.x, BLOCK);
+                sub_to_rows(g, threadIdx.x, NT);
                 __syncthreads();
             }
-            run_stage<LDS, false>(dp, smem, i, ph, cnt, ctl, threadIdx.x, BLOCK);
+            run_stage<LDS, false>(dp, smem, i, ph, cnt, ctl, threadIdx.x, NT);
             __syncthreads();
-            clear_candidates(g, threadIdx.x, BLOCK);
+            clear_candidates(g, threadIdx.x, NT);
             __syncthreads();
-            level_loop<LDS>(dp, smem, ph == HC_THIN || ph == HF_THIN, nlev, cnt, ctl);
-            for (int k = threadIdx.x; k < nlev; k += BLOCK)
+            level_loop<LDS, NT>(dp, smem, ph == HC_THIN || ph == HF_THIN, nlev, cnt, ctl);
+            for (int k = threadIdx.x; k < nlev; k += NT)
                 cnt[k] = 0;
             __syncthreads();
         }
     }
     if (r > 0) {
-        sub_to_rows(g, threadIdx.x, BLOCK);
+        sub_to_rows(g, threadIdx.x, NT);
         __syncthreads();
     }
-    unpack_rows(dp->X, dp->ld, g.H, g.W, g.R, threadIdx.x, BLOCK);
+    unpack_rows(dp->X, dp->ld, g.H, g.W, g.R, threadIdx.x, NT);
 }
 
 // ---------------------------------------------------------------------------
@@ -621,7 +624,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 // Each workgroup claims images in queue order until the queue is empty. When
 // `done` is given (host-mapped memory), done[q] becomes 1 once image q's
 // result is in memory, so the host can hand it out before the launch ends.
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void hasf_filter_kernel(
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void hasf_filter_kernel(
     const ImgDesc* __restrict__ desc, int n, int* __restrict__ next, unsigned* done)
 {
     extern __shared__ uint64_t smem[];
@@ -637,9 +641,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         if (img >= n)
             break;
         if (desc[img].lds)
-            run_image<true>(desc + img, smem, (lds_u32*)cnt, (lds_i32*)ctl);
+            run_image<true, NT>(desc + img, smem, (lds_u32*)cnt, (lds_i32*)ctl);
         else
-            run_image<false>(desc + img, smem, (lds_u32*)cnt, (lds_i32*)ctl);
+            run_image<false, NT>(desc + img, smem, (lds_u32*)cnt, (lds_i32*)ctl);
         if (done) {
             __threadfence();  // each thread's stores of the image reach device scope
             __syncthreads();
@@ -659,16 +663,34 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 // ---------------------------------------------------------------------------
 namespace hasf_detail {
 
-int filter_block() { return BLOCK; }
+// Workgroup size of a launch of n images: with at most one image per CU,
+// 1024 threads per image (a lone image finishes sooner with more waves);
+// beyond that 512, so that two images share a CU and hide each other's
+// barrier stalls (measured on 512x512 r=5: 1024 images at 512 threads
+// 117 K frames/s against 83 K at 1024; one image 2.8 ms against 3.3 ms).
+int filter_block_for(int n, int num_cu)
+{
+    return n <= num_cu ? FILTER_BLOCK_MAX : BLOCK;
+}
 
-hipError_t launch_filter(const ImgDesc* d_desc, int n, int* d_next, int grid, size_t lds_bytes,
+hipError_t launch_filter(const ImgDesc* d_desc, int n, int* d_next, int grid, int block, size_t lds_bytes,
                          hipStream_t stream, unsigned* done)
 {
-    static std::atomic<uint64_t> attr_done{0};
-    const hipError_t e = allow_dyn_lds((const void*)hasf_filter_kernel, 160 * 1024 - 2048, attr_done);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(hasf_filter_kernel, dim3(grid), dim3(BLOCK), lds_bytes, stream, d_desc, n, d_next, done);
+    static std::atomic<uint64_t> attr_512{0}, attr_1024{0};
+    hipError_t e;
+    if (block == FILTER_BLOCK_MAX) {
+        e = allow_dyn_lds((const void*)hasf_filter_kernel<FILTER_BLOCK_MAX>, 160 * 1024 - 2048, attr_1024);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(hasf_filter_kernel<FILTER_BLOCK_MAX>, dim3(grid), dim3(block), lds_bytes, stream, d_desc,
+                           n, d_next, done);
+    } else {
+        e = allow_dyn_lds((const void*)hasf_filter_kernel<BLOCK>, 160 * 1024 - 2048, attr_512);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(hasf_filter_kernel<BLOCK>, dim3(grid), dim3(BLOCK), lds_bytes, stream, d_desc, n,
+                           d_next, done);
+    }
     return hipGetLastError();
 }
 
@@ -692,10 +714,15 @@ int grid_occupancy()
     return blocks;
 }
 
-int filter_occupancy(size_t lds_bytes)
+int filter_occupancy(size_t lds_bytes, int block)
 {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, hasf_filter_kernel, BLOCK, lds_bytes) != hipSuccess) {
+    const hipError_t e = block == FILTER_BLOCK_MAX
+                             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                   &blocks, hasf_filter_kernel<FILTER_BLOCK_MAX>, block, lds_bytes)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, hasf_filter_kernel<BLOCK>,
+                                                                            BLOCK, lds_bytes);
+    if (e != hipSuccess) {
         (void)hipGetLastError();
         return 1;
     }

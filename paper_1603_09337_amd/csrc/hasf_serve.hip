@@ -30,9 +30,10 @@
 #include "hasf_common.h"
 
 namespace hasf_detail {
-hipError_t launch_filter(const ImgDesc* d_desc, int n, int* d_next, int grid, size_t lds_bytes,
+hipError_t launch_filter(const ImgDesc* d_desc, int n, int* d_next, int grid, int block, size_t lds_bytes,
                          hipStream_t stream, unsigned* done);
-int filter_occupancy(size_t lds_bytes);
+int filter_occupancy(size_t lds_bytes, int block);
+int filter_block_for(int n, int num_cu);
 hipError_t launch_grid(const ImgDesc* d_desc, GridCtl* d_ctl, unsigned* d_err, int grid, hipStream_t stream);
 int grid_occupancy();
 void record_error(hasf_ctx* ctx, const char* msg);
@@ -273,15 +274,18 @@ bool launch_lane(hasf_server* s, Lane& ln)
     s->launched_frames += n;
     s->batch_max = std::max(s->batch_max, n);
 
-    const int occ = std::max(1, filter_occupancy(lds_need));
+    // the lanes share the device: count every frame in flight (this launch's
+    // included) against the CUs
+    const int block = filter_block_for((int)std::min<uint64_t>(s->in_flight, INT32_MAX), s->ctx->num_cu);
+    const int occ = std::max(1, filter_occupancy(lds_need, block));
     const int grid = std::min(n, s->ctx->num_cu * occ);
     // h_meta is pinned and not rewritten before this lane's launch has ended,
     // so the copy may run after this call returns
     hipError_t e = hipMemcpyAsync(ln.d_meta, ln.h_meta, 256 + sizeof(ImgDesc) * (size_t)n, hipMemcpyHostToDevice,
                                   ln.stream);
     if (e == hipSuccess)
-        e = launch_filter((const ImgDesc*)(ln.d_meta + 256), n, (int*)ln.d_meta, grid, lds_need, ln.stream,
-                          ln.d_done);
+        e = launch_filter((const ImgDesc*)(ln.d_meta + 256), n, (int*)ln.d_meta, grid, block, lds_need,
+                          ln.stream, ln.d_done);
     if (e == hipSuccess)
         e = hipEventRecord(ln.ev, ln.stream);
     if (e != hipSuccess)

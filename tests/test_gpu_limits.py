@@ -59,3 +59,25 @@ def test_radius_out_of_range_is_refused(r):
     assert e.value.status == hasf.HASF_EINVAL
     ctx().sync()
     assert np.array_equal(host(d), X)
+
+
+def test_batch_larger_than_the_device_uses_smaller_workgroups():
+    # more images than CUs: 512-thread workgroups, two per CU; fewer: 1024
+    # threads per image. Both must give the oracle's result.
+    rng = np.random.default_rng(61)
+    items = []
+    for k in range(300):
+        H, W = int(rng.integers(20, 70)), int(rng.integers(20, 70))
+        items.append((synth.random_binary(H, W, 0.5, 6100 + k), None, int(rng.integers(0, 4))))
+    say("batch of 300 small images")
+    ds = [dev(X) for X, _, _ in items]
+    ctx().filter_batch([(d, None, r) for d, (_, _, r) in zip(ds, items)])
+    ctx().sync()
+    for k, (d, (X, C, r)) in enumerate(zip(ds, items)):
+        assert np.array_equal(host(d), oracle.hasf(X, C, r)), "image %d" % k
+    say("the first 40 of them as their own batch")
+    ds = [dev(X) for X, _, _ in items[:40]]
+    ctx().filter_batch([(d, None, r) for d, (_, _, r) in zip(ds, items[:40])])
+    ctx().sync()
+    for k, (d, (X, C, r)) in enumerate(zip(ds, items[:40])):
+        assert np.array_equal(host(d), oracle.hasf(X, C, r)), "image %d" % k
