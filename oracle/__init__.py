@@ -58,6 +58,9 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = [U8P, U8P, ctypes.c_int, ctypes.c_int]
         f.restype = ctypes.c_long
+    for f in (lib.oracle_homotopic_thin_n, lib.oracle_homotopic_thicken_n):
+        f.argtypes = [U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        f.restype = ctypes.c_long
     lib.oracle_hc.argtypes = [U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.oracle_hc.restype = ctypes.c_long
     lib.oracle_hf.argtypes = [U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
@@ -146,18 +149,20 @@ def thicken_p(S, V, P, queue: bool = False):
     return s, rounds
 
 
-def homotopic_thin(X, K=None) -> np.ndarray:
+def homotopic_thin(X, K=None, n: int = 8) -> np.ndarray:
+    """H(X, K) (Sec. 2) for the pair (n, n-bar) = (8, 4) or (4, 8)."""
     x = np.ascontiguousarray(X, dtype=np.uint8).copy()
     k, kp = _opt_u8(K)
-    _check(_load().oracle_homotopic_thin(x.ctypes.data_as(U8P), kp, x.shape[0], x.shape[1]),
+    _check(_load().oracle_homotopic_thin_n(x.ctypes.data_as(U8P), kp, x.shape[0], x.shape[1], n),
            "homotopic_thin")
     return x
 
 
-def homotopic_thicken(Y, V) -> np.ndarray:
+def homotopic_thicken(Y, V, n: int = 8) -> np.ndarray:
+    """*H(Y, V) (Sec. 2) for the pair (n, n-bar) = (8, 4) or (4, 8)."""
     y = np.ascontiguousarray(Y, dtype=np.uint8).copy()
     v, vp = _opt_u8(V)
-    _check(_load().oracle_homotopic_thicken(y.ctypes.data_as(U8P), vp, y.shape[0], y.shape[1]),
+    _check(_load().oracle_homotopic_thicken_n(y.ctypes.data_as(U8P), vp, y.shape[0], y.shape[1], n),
            "homotopic_thicken")
     return y
 

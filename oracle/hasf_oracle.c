@@ -433,11 +433,11 @@ static void normalise(uint8_t* X, size_t N)
         X[p] = X[p] != 0;
 }
 
-/* H(X, K): priority = squared distance to the background, the outside of the
- * window included. */
-long oracle_homotopic_thin(uint8_t* X, const uint8_t* K, int H, int W)
+/* H(X, K) for the pair (n, n-bar) (n = 8: (8,4); n = 4: (4,8)): priority =
+ * squared distance to the background, the outside of the window included. */
+long oracle_homotopic_thin_n(uint8_t* X, const uint8_t* K, int H, int W, int n)
 {
-    if (H < 1 || W < 1)
+    if (H < 1 || W < 1 || (n != 8 && n != 4))
         return ORACLE_EINVAL;
     const size_t N = (size_t)H * W;
     normalise(X, N);
@@ -451,15 +451,20 @@ long oracle_homotopic_thin(uint8_t* X, const uint8_t* K, int H, int W)
         bg[p] = !X[p];
     long rc = oracle_edt_sq(bg, H, W, 1, P);
     if (rc == 0)
-        rc = subfield_schedule(0, X, K, P, H, W, lut84());
+        rc = subfield_schedule(0, X, K, P, H, W, lut_for(n));
     free(bg); free(P);
     return rc;
 }
 
-/* *H(Y, V): priority = squared distance to Y. */
-long oracle_homotopic_thicken(uint8_t* Y, const uint8_t* V, int H, int W)
+long oracle_homotopic_thin(uint8_t* X, const uint8_t* K, int H, int W)
 {
-    if (H < 1 || W < 1)
+    return oracle_homotopic_thin_n(X, K, H, W, 8);
+}
+
+/* *H(Y, V) for the pair (n, n-bar): priority = squared distance to Y. */
+long oracle_homotopic_thicken_n(uint8_t* Y, const uint8_t* V, int H, int W, int n)
+{
+    if (H < 1 || W < 1 || (n != 8 && n != 4))
         return ORACLE_EINVAL;
     const size_t N = (size_t)H * W;
     normalise(Y, N);
@@ -468,9 +473,14 @@ long oracle_homotopic_thicken(uint8_t* Y, const uint8_t* V, int H, int W)
         return ORACLE_ENOMEM;
     long rc = oracle_edt_sq(Y, H, W, 0, P);
     if (rc == 0)
-        rc = subfield_schedule(1, Y, V, P, H, W, lut84());
+        rc = subfield_schedule(1, Y, V, P, H, W, lut_for(n));
     free(P);
     return rc;
+}
+
+long oracle_homotopic_thicken(uint8_t* Y, const uint8_t* V, int H, int W)
+{
+    return oracle_homotopic_thicken_n(Y, V, H, W, 8);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -113,3 +113,47 @@ def test_planted_table_mistake_is_caught():
     bad, _ = oracle.thin_p_lut(X, None, P, lut)
     assert tc.topology(good) == tc.topology(X)
     assert tc.topology(bad) != tc.topology(X)
+
+
+# The (4,8) pair in the standalone entry points: pinned to a raster-order
+# implementation with a table from the global definition (scipy labelling),
+# to the (4,8) topology, and to ultimacy under that table.
+_T48 = None
+
+
+def _table48():
+    global _T48
+    if _T48 is None:
+        _T48 = np.array([tc.global_simple48(m) for m in range(256)], dtype=bool)
+    return _T48
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_homotopic_thin_48(idx):
+    S = _images()[idx]
+    rng = np.random.default_rng(50 + idx)
+    K = ((rng.random(S.shape) < 0.05) & (S != 0)).astype(np.uint8)
+    T = oracle.homotopic_thin(S, K, n=4)
+    P = tc.edt_brute((S == 0).astype(np.uint8), True)
+    assert np.array_equal(T, tc.sequential_schedule(0, S, K, P, table=list(_table48())))
+    assert tc.topology48(T) == tc.topology48(S)
+    assert ((K != 0) <= (T != 0)).all() and ((T != 0) <= (S != 0)).all()
+    assert not (_table48()[tc.neighbourhood_codes(T)] & (T != 0) & (K == 0)).any()
+
+
+def test_the_pair_matters_for_standalone_thinning():
+    diff = sum(int((oracle.homotopic_thin(S, None, n=4) != oracle.homotopic_thin(S)).sum()) for S in _images())
+    assert diff > 0
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_homotopic_thicken_48(idx):
+    S = _images()[idx]
+    V = tc.dilate_stamp(S, 4).astype(np.uint8)
+    U = oracle.homotopic_thicken(S, V, n=4)
+    P = tc.edt_brute(S, False)
+    assert np.array_equal(U, tc.sequential_schedule(1, S, V, P, table=list(_table48())))
+    assert tc.topology48(U) == tc.topology48(S)
+    assert ((S != 0) <= (U != 0)).all() and ((U != 0) <= (V != 0) | (S != 0)).all()
+    # ultimate: no point of V outside U can be added (simple for U plus it)
+    assert not (_table48()[tc.neighbourhood_codes(U)] & (U == 0) & (V != 0)).any()

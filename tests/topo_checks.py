@@ -148,15 +148,17 @@ def disk_image(R: int, margin: int = 12) -> np.ndarray:
     return (((ii - c) ** 2 + (jj - c) ** 2) <= R * R).astype(np.uint8)
 
 
-def sequential_schedule(mode: int, S: np.ndarray, B, P: np.ndarray) -> np.ndarray:
+def sequential_schedule(mode: int, S: np.ndarray, B, P: np.ndarray, table=None) -> np.ndarray:
     """Second, structurally different implementation of the distance-ordered
     subfield schedule: inside each subfield pass, points are updated in place in
     raster order (no separate deletion list). Same result as the simultaneous
-    pass because two points of one subfield are never 8-adjacent."""
+    pass because two points of one subfield are never 8-adjacent. table: the
+    simple-point predicate per neighbourhood code (default: (8,4), Yokoi)."""
     S = (np.asarray(S) != 0).astype(np.uint8).copy()
     H, W = S.shape
     Bm = np.zeros((H, W), dtype=bool) if B is None else (np.asarray(B) != 0)
-    table = [yokoi_simple(m) for m in range(256)]
+    if table is None:
+        table = [yokoi_simple(m) for m in range(256)]
     cand = (S == 1) & ~Bm if mode == 0 else (S == 0) & Bm
     levels = sorted(set(P[cand].tolist()))
 
@@ -216,3 +218,19 @@ def euler48_quads(X: np.ndarray) -> int:
 
 def topology48(X: np.ndarray):
     return components4(X), components8_complement(X), euler48_quads(X)
+
+
+def global_simple48(m: int) -> bool:
+    """The global definition for the (4,8) pair: removing x changes neither the
+    number of 4-components of X nor that of 8-components of the complement, on
+    the 3x3 configuration padded with background."""
+    img = np.zeros((5, 5), dtype=np.uint8)
+    img[2, 2] = 1
+    for k, (dy, dx) in enumerate(NB):
+        img[2 + dy, 2 + dx] = (m >> k) & 1
+    before_o = ndimage.label(img, FOUR)[1]
+    before_b = ndimage.label(1 - img, EIGHT)[1]
+    img[2, 2] = 0
+    after_o = ndimage.label(img, FOUR)[1]
+    after_b = ndimage.label(1 - img, EIGHT)[1]
+    return before_o == after_o and before_b == after_b
