@@ -141,6 +141,17 @@ hasf_status hasf_homotopic_thicken(hasf_ctx* ctx, uint8_t* Y, const uint8_t* V, 
                                    int64_t ld);
 
 /*
+ * hasf_homotopic_thin / hasf_homotopic_thicken for the connectivity pair
+ * chosen by conn (Sec. 2): 8 (or 0) for 8-connected objects and a 4-connected
+ * background, 4 for 4-connected objects and an 8-connected background. The
+ * priorities do not depend on the pair. HASF_EINVAL for other conn.
+ */
+hasf_status hasf_homotopic_thin_conn(hasf_ctx* ctx, uint8_t* X, const uint8_t* K, int H, int W,
+                                     int64_t ld, int conn);
+hasf_status hasf_homotopic_thicken_conn(hasf_ctx* ctx, uint8_t* Y, const uint8_t* V, int H, int W,
+                                        int64_t ld, int conn);
+
+/*
  * HASF of order r with constraint set C (Sec. 2):
  *   X <- HF_r o HC_r o ... o HF_1 o HC_1 (X), in place, where for radius i
  *   HC_i(X) = *H(Y, V), Y = H(X, eps_i(X) u C), V = delta_i(Y) n X      (eq. i)

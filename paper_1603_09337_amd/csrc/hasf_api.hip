@@ -578,12 +578,16 @@ hasf_status hasf_filter_batch(hasf_ctx* ctx, const hasf_image* imgs, int n)
 // ---------------------------------------------------------------------------
 namespace {
 
-hasf_status run_topo(hasf_ctx* ctx, uint8_t* X, const uint8_t* B, int H, int W, int64_t ld, bool thin,
+hasf_status run_topo(hasf_ctx* ctx, uint8_t* X, const uint8_t* B, int H, int W, int64_t ld, bool thin, int conn,
                      const char* what)
 {
     hasf_status s = check_image(ctx, X, H, W, ld, what);
     if (s)
         return s;
+    if (conn != 0 && conn != 8 && conn != 4) {
+        set_err(ctx, "%s: conn = %d (0 or 8: the (8,4) pair; 4: the (4,8) pair)", what, conn);
+        return HASF_EINVAL;
+    }
     if (!thin && !B) {
         set_err(ctx, "%s: V must not be NULL", what);
         return HASF_EINVAL;
@@ -627,6 +631,7 @@ hasf_status run_topo(hasf_ctx* ctx, uint8_t* X, const uint8_t* B, int H, int W, 
     a.H = H;
     a.W = W;
     a.thin = thin ? 1 : 0;
+    a.conn4 = conn == 4 ? 1 : 0;
     a.lds = lds ? 1 : 0;
     a.P = (const uint32_t*)(base + oP);
     a.planes = (uint64_t*)(base + oPl);
@@ -647,12 +652,24 @@ extern "C" {
 
 hasf_status hasf_homotopic_thin(hasf_ctx* ctx, uint8_t* X, const uint8_t* K, int H, int W, int64_t ld)
 {
-    return run_topo(ctx, X, K, H, W, ld, true, "hasf_homotopic_thin");
+    return run_topo(ctx, X, K, H, W, ld, true, 8, "hasf_homotopic_thin");
 }
 
 hasf_status hasf_homotopic_thicken(hasf_ctx* ctx, uint8_t* Y, const uint8_t* V, int H, int W, int64_t ld)
 {
-    return run_topo(ctx, Y, V, H, W, ld, false, "hasf_homotopic_thicken");
+    return run_topo(ctx, Y, V, H, W, ld, false, 8, "hasf_homotopic_thicken");
+}
+
+hasf_status hasf_homotopic_thin_conn(hasf_ctx* ctx, uint8_t* X, const uint8_t* K, int H, int W, int64_t ld,
+                                     int conn)
+{
+    return run_topo(ctx, X, K, H, W, ld, true, conn, "hasf_homotopic_thin_conn");
+}
+
+hasf_status hasf_homotopic_thicken_conn(hasf_ctx* ctx, uint8_t* Y, const uint8_t* V, int H, int W, int64_t ld,
+                                        int conn)
+{
+    return run_topo(ctx, Y, V, H, W, ld, false, conn, "hasf_homotopic_thicken_conn");
 }
 
 }  // extern "C"

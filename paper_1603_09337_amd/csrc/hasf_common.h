@@ -207,6 +207,7 @@ struct TopoArgs {
     long long ld;
     int H, W;
     int thin;
+    int conn4;              // 1: the (4,8) pair; 0: (8,4)
     int lds;                // S and M planes in LDS
     const uint32_t* P;      // priorities, pitch W
     uint64_t* planes;       // S, M (when lds == 0), Bp

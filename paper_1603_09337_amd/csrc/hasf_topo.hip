@@ -79,7 +79,7 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     g.Dp = nullptr;
     g.hasK = false;
     g.hasD = false;
-    g.conn4 = false;
+    g.conn4 = a.conn4 != 0;
     g.eidx = nullptr;
     g.emsk = nullptr;
     const int N = a.H * a.W;

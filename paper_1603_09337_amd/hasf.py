@@ -86,12 +86,16 @@ _lib.hasf_edt_sq.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int6
                              ctypes.c_int64]
 _lib.hasf_homotopic_thin.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64]
 _lib.hasf_homotopic_thicken.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64]
+_lib.hasf_homotopic_thin_conn.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int]
+_lib.hasf_homotopic_thicken_conn.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                             ctypes.c_int]
 _lib.hasf_filter.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int]
 _lib.hasf_filter_cd.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
                                 ctypes.c_int]
 _lib.hasf_filter_batch.argtypes = [_vp, ctypes.POINTER(_Image), ctypes.c_int]
 for _f in ("hasf_create", "hasf_set_stream", "hasf_sync", "hasf_simple_lut", "hasf_edt_sq",
-           "hasf_homotopic_thin", "hasf_homotopic_thicken", "hasf_filter", "hasf_filter_cd",
+           "hasf_homotopic_thin", "hasf_homotopic_thicken", "hasf_homotopic_thin_conn",
+           "hasf_homotopic_thicken_conn", "hasf_filter", "hasf_filter_cd",
            "hasf_filter_batch"):
     getattr(_lib, _f).restype = ctypes.c_int
 
@@ -202,20 +206,26 @@ class Context:
                                      out.stride(0)))
         return out
 
-    def homotopic_thin(self, X, K=None):
+    def homotopic_thin(self, X, K=None, conn: int = 8):
         H, W, ld = _img(X, "X", self.device)
         _companion(K, X, "K")
         self._stream()
-        self._check(_lib.hasf_homotopic_thin(self._h, _ptr(X), _ptr(K), H, W, ld))
+        if conn == 8:
+            self._check(_lib.hasf_homotopic_thin(self._h, _ptr(X), _ptr(K), H, W, ld))
+        else:
+            self._check(_lib.hasf_homotopic_thin_conn(self._h, _ptr(X), _ptr(K), H, W, ld, conn))
         return X
 
-    def homotopic_thicken(self, Y, V):
+    def homotopic_thicken(self, Y, V, conn: int = 8):
         H, W, ld = _img(Y, "Y", self.device)
         if V is None:
             raise ValueError("V must not be None")
         _companion(V, Y, "V")
         self._stream()
-        self._check(_lib.hasf_homotopic_thicken(self._h, _ptr(Y), _ptr(V), H, W, ld))
+        if conn == 8:
+            self._check(_lib.hasf_homotopic_thicken(self._h, _ptr(Y), _ptr(V), H, W, ld))
+        else:
+            self._check(_lib.hasf_homotopic_thicken_conn(self._h, _ptr(Y), _ptr(V), H, W, ld, conn))
         return Y
 
     def filter(self, X, C=None, r: int = 1, D=None, conn: int = 8, order: int = 0):
