@@ -15,6 +15,9 @@ using namespace hasf_dev;
 
 using hasf_detail::TopoArgs;
 
+// threads of the one workgroup that runs a standalone thinning or thickening
+constexpr int TOPO_BLOCK = 1024;
+
 namespace {
 
 typedef __attribute__((address_space(1))) uint32_t g32;
@@ -35,16 +38,16 @@ __device__ unsigned block_exclusive_scan(unsigned v, unsigned* out_prefix, unsig
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned acc = 0;
-        for (int w = 0; w < BLOCK / 64; ++w) {
+        for (int w = 0; w < TOPO_BLOCK / 64; ++w) {
             const unsigned t = lds_tmp[w];
             lds_tmp[w] = acc;
             acc += t;
         }
-        lds_tmp[BLOCK / 64] = acc;
+        lds_tmp[TOPO_BLOCK / 64] = acc;
     }
     __syncthreads();
     *out_prefix = lds_tmp[wave] + x - v;
-    const unsigned total = lds_tmp[BLOCK / 64];
+    const unsigned total = lds_tmp[TOPO_BLOCK / 64];
     __syncthreads();
     return total;
 }
@@ -59,7 +62,7 @@ __device__ __forceinline__ bool bit_at(PP plane, int WW, int i, int j)
 template <bool LDS>
 __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
 {
-    __shared__ unsigned tmp[BLOCK / 64 + 1];
+    __shared__ unsigned tmp[TOPO_BLOCK / 64 + 1];
     __shared__ int ctl[CTL_WORDS];
     Img<LDS> g;
     g.ctl = (lds_i32*)ctl;
@@ -86,19 +89,19 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     const int WW = g.WW;
 
     // X -> R, B -> Bp (row-major); R is read below until the sub-images are built
-    pack_rows(a.X, (const uint8_t*)nullptr, a.ld, a.H, a.W, g.R, (glb_u64*)nullptr, threadIdx.x, BLOCK);
+    pack_rows(a.X, (const uint8_t*)nullptr, a.ld, a.H, a.W, g.R, (glb_u64*)nullptr, threadIdx.x, TOPO_BLOCK);
     if (a.B)
-        pack_rows(a.B, (const uint8_t*)nullptr, a.ld, a.H, a.W, Bp, (glb_u64*)nullptr, threadIdx.x, BLOCK);
+        pack_rows(a.B, (const uint8_t*)nullptr, a.ld, a.H, a.W, Bp, (glb_u64*)nullptr, threadIdx.x, TOPO_BLOCK);
     else
-        for (int q = threadIdx.x; q < g.NWD; q += BLOCK)
+        for (int q = threadIdx.x; q < g.NWD; q += TOPO_BLOCK)
             Bp[q] = 0;
     glb_u64* bm = (glb_u64*)a.bitmap;
-    for (unsigned long long q = threadIdx.x; q < a.nbw; q += BLOCK)
+    for (unsigned long long q = threadIdx.x; q < a.nbw; q += TOPO_BLOCK)
         bm[q] = 0;
     __syncthreads();
 
     // mark the priority values of the candidates
-    for (int p = threadIdx.x; p < N; p += BLOCK) {
+    for (int p = threadIdx.x; p < N; p += TOPO_BLOCK) {
         const int i = p / a.W, j = p - i * a.W;
         const bool s = bit_at(g.R, WW, i, j), b = bit_at(Bp, WW, i, j);
         if (a.thin ? (s && !b) : (!s && b)) {
@@ -111,7 +114,7 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     __syncthreads();
 
     // rank base of every bitmap word (prefix popcount, chunked per thread)
-    const unsigned long long chunk = (a.nbw + BLOCK - 1) / BLOCK;
+    const unsigned long long chunk = (a.nbw + TOPO_BLOCK - 1) / TOPO_BLOCK;
     const unsigned long long c0 = threadIdx.x * chunk, c1 = min(a.nbw, c0 + chunk);
     unsigned local = 0;
     for (unsigned long long q = c0; q < c1; ++q)
@@ -124,12 +127,12 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
         pre += __popcll(bm[q]);
     }
     g32* hist = (g32*)a.hist;
-    for (unsigned k = threadIdx.x; k < nlev; k += BLOCK)
+    for (unsigned k = threadIdx.x; k < nlev; k += TOPO_BLOCK)
         hist[k] = 0;
     __syncthreads();
 
     // count candidates per level
-    for (int p = threadIdx.x; p < N; p += BLOCK) {
+    for (int p = threadIdx.x; p < N; p += TOPO_BLOCK) {
         const int i = p / a.W, j = p - i * a.W;
         const bool s = bit_at(g.R, WW, i, j), b = bit_at(Bp, WW, i, j);
         if (a.thin ? (s && !b) : (!s && b)) {
@@ -144,7 +147,7 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     __syncthreads();
     // exclusive offsets per level
     {
-        const unsigned long long hc = (nlev + BLOCK - 1) / BLOCK;
+        const unsigned long long hc = (nlev + TOPO_BLOCK - 1) / TOPO_BLOCK;
         const unsigned long long h0 = threadIdx.x * hc, h1 = min((unsigned long long)nlev, h0 + hc);
         unsigned loc = 0;
         for (unsigned long long k = h0; k < h1; ++k)
@@ -160,7 +163,7 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     __syncthreads();
     // scatter: afterwards hist[k] is the end of level k
     g32* ent = (g32*)a.ent;
-    for (int p = threadIdx.x; p < N; p += BLOCK) {
+    for (int p = threadIdx.x; p < N; p += TOPO_BLOCK) {
         const int i = p / a.W, j = p - i * a.W;
         const bool s = bit_at(g.R, WW, i, j), b = bit_at(Bp, WW, i, j);
         if (a.thin ? (s && !b) : (!s && b)) {
@@ -175,9 +178,9 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
         }
     }
     __syncthreads();
-    rows_to_sub(g, threadIdx.x, BLOCK);
+    rows_to_sub(g, threadIdx.x, TOPO_BLOCK);
     __syncthreads();
-    clear_candidates(g, threadIdx.x, BLOCK);  // R is no longer needed
+    clear_candidates(g, threadIdx.x, TOPO_BLOCK);  // R is no longer needed
     Sched sc;
     sched_reset(g, sc);
     __syncthreads();
@@ -186,23 +189,23 @@ __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
     for (unsigned k = 0; k < nlev; ++k) {
         const unsigned e0 = k ? hist[k - 1] : 0u, e1 = hist[k];
         const int ser = ++sc.serial;
-        for (unsigned t = e0 + threadIdx.x; t < e1; t += BLOCK) {
+        for (unsigned t = e0 + threadIdx.x; t < e1; t += TOPO_BLOCK) {
             const unsigned p = ent[t];
             const int i = (int)(p / (unsigned)a.W), j = (int)(p - (unsigned)i * (unsigned)a.W);
             activate_pixel(g, i, j, ser);
         }
         __syncthreads();
-        run_rounds(g, a.thin != 0, sc);
+        run_rounds<LDS, TOPO_BLOCK>(g, a.thin != 0, sc);
     }
     __syncthreads();
-    sub_to_rows(g, threadIdx.x, BLOCK);
+    sub_to_rows(g, threadIdx.x, TOPO_BLOCK);
     __syncthreads();
-    unpack_rows(a.X, a.ld, a.H, a.W, g.R, threadIdx.x, BLOCK);
+    unpack_rows(a.X, a.ld, a.H, a.W, g.R, threadIdx.x, TOPO_BLOCK);
 }
 
 }  // namespace
 
-__global__ __launch_bounds__(BLOCK) void hasf_topo_kernel(TopoArgs a)
+__global__ __launch_bounds__(TOPO_BLOCK) void hasf_topo_kernel(TopoArgs a)
 {
     extern __shared__ uint64_t smem[];
     if (a.lds)
@@ -219,7 +222,7 @@ hipError_t launch_topo(const TopoArgs& a, size_t lds_bytes, hipStream_t stream)
     const hipError_t e = allow_dyn_lds((const void*)hasf_topo_kernel, 160 * 1024 - 4096, attr_done);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(hasf_topo_kernel, dim3(1), dim3(BLOCK), lds_bytes, stream, a);
+    hipLaunchKernelGGL(hasf_topo_kernel, dim3(1), dim3(TOPO_BLOCK), lds_bytes, stream, a);
     return hipGetLastError();
 }
 
