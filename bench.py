@@ -28,6 +28,10 @@ Beside it, on the same GPU:
 * cpu_baseline: the CPU oracle on a small sample of the 512x512 images
   (single thread).
 Prints one JSON line.
+
+The served streams run one launch lane per hardware queue. --hw-queues Q
+(default 16; 0 keeps the environment's) sets GPU_MAX_HW_QUEUES for this
+process before torch, and so the HIP runtime, starts.
 """
 from __future__ import annotations
 
@@ -39,6 +43,9 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# hardware queues of the process, set from --hw-queues before the HIP runtime
+# starts (the served streams run one launch lane per queue)
+HW_QUEUES = 4
 
 H = W = 512
 R = 5
@@ -71,7 +78,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--mixed-seconds", type=float, default=10.0)
     ap.add_argument("--rate", type=float, default=2000.0)
-    ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--lanes", type=int, default=0)  # 0: one per hardware queue
+    ap.add_argument("--hw-queues", type=int, default=16)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-edt", action="store_true")
@@ -200,7 +208,7 @@ def bench_served(ctx, a, src, Cd):
     import numpy as np
     import torch
     from paper_1603_09337_amd import hasf, synth
-    out = {}
+    out = {"hw_queues": HW_QUEUES, "lanes": a.lanes or min(hasf.HASF_SERVE_LANES_MAX, HW_QUEUES)}
     rng = np.random.Generator(np.random.PCG64(synth.SEED_STREAM + 1))
 
     # 512x512 r=5 at the offered rate
@@ -306,7 +314,11 @@ def bench_served(ctx, a, src, Cd):
 
 
 def main():
+    global HW_QUEUES
     a = parse()
+    if a.hw_queues > 0:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(a.hw_queues)
+    HW_QUEUES = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
     if a.gpus != 1:
         print("bench.py: libhasf runs on one GPU; --gpus %d is not supported (use --gpus 1)" % a.gpus,
               file=sys.stderr)

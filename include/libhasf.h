@@ -231,7 +231,9 @@ hasf_status hasf_filter_batch(hasf_ctx* ctx, const hasf_image* imgs, int n);
 
 typedef struct {
     size_t pool_bytes;     /* device memory for frame scratch; 0 = the context's hbm_budget */
-    int lanes;             /* launches in flight at once, 1..HASF_SERVE_LANES_MAX (0 = 4) */
+    int lanes;             /* launches in flight at once, 1..HASF_SERVE_LANES_MAX; 0 = one per hardware
+                              queue of the process (GPU_MAX_HW_QUEUES, 4 if unset), at most
+                              HASF_SERVE_LANES_MAX. Lanes beyond the hardware queues share them. */
     int max_batch;         /* frames per launch (0 = 1024) */
     int max_pending;       /* submitted but not yet admitted; beyond it submit returns HASF_EAGAIN (0 = 1 << 20) */
     unsigned flags;        /* 0 (HASF_SERVE_PERSISTENT is switched off) */

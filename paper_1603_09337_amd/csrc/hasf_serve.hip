@@ -17,6 +17,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstdio>
+#include <cstdlib>
 #include <cstddef>
 #include <cstring>
 #include <deque>
@@ -404,6 +405,21 @@ void free_server(hasf_server* s)
 
 extern "C" {
 
+// Lanes by default: one per hardware queue the HIP runtime gives the process
+// (GPU_MAX_HW_QUEUES, 4 when unset). Launches on streams beyond the hardware
+// queues share a queue and run one after the other, so more lanes than
+// queues add nothing.
+static int default_lanes()
+{
+    int q = 4;
+    if (const char* v = std::getenv("GPU_MAX_HW_QUEUES")) {
+        const int n = std::atoi(v);
+        if (n > 0)
+            q = n;
+    }
+    return std::max(1, std::min(q, (int)HASF_SERVE_LANES_MAX));
+}
+
 hasf_status hasf_serve(hasf_ctx* ctx, const hasf_serve_opts* opts, hasf_server** out)
 {
     if (!ctx || !out) {
@@ -430,7 +446,7 @@ hasf_status hasf_serve(hasf_ctx* ctx, const hasf_serve_opts* opts, hasf_server**
     s->max_pending = o.max_pending ? o.max_pending : (1 << 20);
     const size_t pool_bytes = (o.pool_bytes ? o.pool_bytes : ctx->hbm_budget) / 256 * 256;
     s->lds_cap = std::min(ctx->lds_per_block, (size_t)160 * 1024) - 2048;
-    s->lanes.resize(o.lanes ? o.lanes : 4);
+    s->lanes.resize(o.lanes ? o.lanes : default_lanes());
     hipSetDevice(ctx->device);
     hipError_t e = hipMalloc((void**)&s->pool_mem, std::max(pool_bytes, (size_t)256));
     const size_t meta = std::max(256 + sizeof(ImgDesc) * (size_t)s->max_batch, GRID_DESC_OFF + sizeof(ImgDesc));
