@@ -86,3 +86,44 @@ def test_binding_refuses_host_and_malformed_tensors():
             hasf._img(t, "X")
     with pytest.raises(ValueError):
         hasf._image((torch.zeros((4, 4), dtype=torch.uint8), None, 1))
+
+
+C_PROGRAM = r"""
+#include <stdio.h>
+#include "libhasf.h"
+int main(void)
+{
+    uint32_t bits[8];
+    hasf_status st = hasf_simple_lut(8, bits);
+    int n = 0;
+    for (int m = 0; m < 256; ++m)
+        n += (bits[m >> 5] >> (m & 31)) & 1u;
+    hasf_image im = {0};
+    hasf_serve_opts so = {0};
+    hasf_opts o = {0};
+    (void)im; (void)so; (void)o;
+    printf("%d %d %s\n", (int)st, n, hasf_strerror(HASF_EINVAL));
+    return st == HASF_OK && n == 116 && hasf_simple_lut(3, bits) == HASF_EINVAL ? 0 : 1;
+}
+"""
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    # the boundary is a C ABI: a C99 program compiles against the header with
+    # -pedantic -Werror, links against the library and calls its host-only
+    # entry points (no GPU needed)
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not found")
+    hasf, _ = _lib()
+    libdir = os.path.dirname(hasf.LIB_PATH)
+    src = tmp_path / "use_hasf.c"
+    src.write_text(C_PROGRAM)
+    exe = tmp_path / "use_hasf"
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                           os.path.join(ROOT, "include"), str(src), "-o", str(exe), "-L", libdir, "-lhasf",
+                           "-Wl,-rpath," + libdir])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.split()[:2] == ["0", "116"]
