@@ -20,6 +20,9 @@ typedef __attribute__((address_space(3))) uint8_t lds_u8;
 typedef __attribute__((address_space(1))) uint8_t glb_u8;
 typedef __attribute__((address_space(3))) uint16_t lds_u16;
 typedef __attribute__((address_space(3))) int lds_i32;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) u32x4 lds_u4;
+typedef __attribute__((address_space(1))) u32x4 glb_u4;
 
 enum StageMode {
     HC_THIN = 0,     // features = complement u outside; base = S \ K; saves S into A
@@ -502,13 +505,24 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
             const int nw = rows * WW;
             lds_i32* cnt = lcnt + (sc.npass & 1);
             // collect: flagged words whose activated candidates are still live;
-            // every lane runs the same number of iterations (wave-wide prefix)
+            // every lane runs the same number of iterations (wave-wide prefix).
+            // The four words' M and S are loaded with their flags, flagged or
+            // not, so the live test waits for one round trip, not three (b0 is
+            // a multiple of 4 below nw <= SUB, and SUB is a multiple of 4, so
+            // the four words lie in the sub-image)
+            using U4 = typename std::conditional<LDS, const lds_u4*, const glb_u4*>::type;
             const int niter = (nw + 4 * NT - 1) / (4 * NT);
             for (int it = 0; it < niter; ++it) {
                 const int b0 = 4 * threadIdx.x + it * 4 * NT;
                 unsigned f4 = 0;
-                if (b0 < nw)
+                u32x4 m4 = {0u, 0u, 0u, 0u}, s4 = m4;
+                if (b0 < nw) {
                     f4 = *(const typename std::conditional<LDS, lds_u32*, glb_u32*>::type)(Ds + b0);
+                    m4 = *(U4)(Ms + b0);
+                    s4 = *(U4)(Ss + b0);
+                }
+                const uint32_t live[4] = {m4.x & (s4.x ^ flip), m4.y & (s4.y ^ flip), m4.z & (s4.z ^ flip),
+                                          m4.w & (s4.w ^ flip)};
                 unsigned nl = 0;
                 int q0 = 0, q1 = 0, q2 = 0, q3 = 0;
                 if (f4) {
@@ -516,7 +530,7 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int q = b0 + j;
-                        if (((f4 >> (8 * j)) & 0xFFu) && q < nw && (Ms[q] & (Ss[q] ^ flip))) {
+                        if (((f4 >> (8 * j)) & 0xFFu) && q < nw && live[j]) {
                             if (nl == 0) q0 = q;
                             else if (nl == 1) q1 = q;
                             else if (nl == 2) q2 = q;
