@@ -55,9 +55,9 @@ typedef enum {
 typedef struct hasf_ctx hasf_ctx;
 
 /* Defaults of hasf_opts.grid_min_pixels and hasf_opts.batch_grid_min_pixels.
- * A lone image of up to about 1.1 Mpx is filtered faster by one workgroup
+ * A lone image of up to about 1.4 Mpx is filtered faster by one workgroup
  * than by a grid of them (both measured at r = 3, 5, 8). */
-#define HASF_GRID_MIN_PIXELS_DEFAULT (((size_t)1 << 20) + ((size_t)1 << 17))
+#define HASF_GRID_MIN_PIXELS_DEFAULT (((size_t)1 << 20) + ((size_t)3 << 17))
 #define HASF_BATCH_GRID_MIN_PIXELS_DEFAULT ((size_t)1 << 23)
 
 /*
