@@ -429,18 +429,35 @@ __device__ __forceinline__ bool rounds_grid(const Img<false>& g, GridSync& gs, i
             const int nchunk = (nw4 + GRID_CHUNK * tn - 1) / (GRID_CHUNK * tn);  // uniform
             bool changed = false;
             for (int ch = 0; ch < nchunk; ++ch) {
+                // the four words' M and S come with their flags (one round
+                // trip), so only flagged words with live candidates are listed
+                // (4 * q4 + 3 < roundup4(nw) <= SUB: in the sub-image)
                 uint32_t f4[GRID_CHUNK];
+                u32x4 m4[GRID_CHUNK], s4[GRID_CHUNK];
 #pragma unroll
                 for (int k = 0; k < GRID_CHUNK; ++k) {
                     const int q4 = t0 + (ch * GRID_CHUNK + k) * tn;
-                    f4[k] = q4 < nw4 ? D4[q4] : 0u;
+                    f4[k] = 0u;
+                    m4[k] = s4[k] = u32x4{0u, 0u, 0u, 0u};
+                    if (q4 < nw4) {
+                        f4[k] = D4[q4];
+                        m4[k] = *(const glb_u4*)(pp.Ms + 4 * q4);
+                        s4[k] = *(const glb_u4*)(pp.Ss + 4 * q4);
+                    }
                 }
                 unsigned nl = 0;
 #pragma unroll
                 for (int k = 0; k < GRID_CHUNK; ++k) {
                     if (f4[k]) {
+                        const int q0 = 4 * (t0 + (ch * GRID_CHUNK + k) * tn);
                         D4[t0 + (ch * GRID_CHUNK + k) * tn] = 0u;
-                        nl += __popc(f4[k] & 0x01010101u);
+                        uint32_t keep = 0u;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (((f4[k] >> (8 * j)) & 0xFFu) && q0 + j < nw && (m4[k][j] & (s4[k][j] ^ flip)))
+                                keep |= 1u << (8 * j);
+                        f4[k] = keep;
+                        nl += __popc(keep);
                     }
                 }
                 // list counts alternate between chunks (sc.npass counts them);
