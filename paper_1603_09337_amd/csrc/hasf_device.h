@@ -23,6 +23,10 @@ typedef __attribute__((address_space(3))) int lds_i32;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) u32x4 lds_u4;
 typedef __attribute__((address_space(1))) u32x4 glb_u4;
+typedef __attribute__((address_space(1))) uint16_t glb_u16;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) u32x2 lds_u2;
+typedef __attribute__((address_space(1))) u32x2 glb_u2;
 
 enum StageMode {
     HC_THIN = 0,     // features = complement u outside; base = S \ K; saves S into A
@@ -251,7 +255,8 @@ __device__ void clear_candidates(const Img<LDS>& g, int t0, int tn)
 // serial number, uniform across the workgroup and strictly increasing within
 // a phase. chg holds the serial of the last pass that changed a pixel;
 // prod[s] the serial of the last activation or pass that flagged a word of
-// sub-image s; cnt[2] are the live-list lengths of alternate passes. A pass
+// sub-image s; cnt[2] are the shared live-list lengths of alternate passes
+// that use one. A pass
 // of sub-image s runs only if prod[s] grew since it last ran; a round changed
 // the set iff chg exceeds the serial at the start of the round. These words
 // are only written between the barriers that separate them from their
@@ -262,7 +267,7 @@ enum { CTL_CHG = 0, CTL_CNT = 2, CTL_PROD = 4, CTL_WORDS = 8 };
 // per-phase scheduling state (uniform registers)
 struct Sched {
     int serial;       // last serial handed out
-    int npass;        // executed passes (selects the live-list length word)
+    int npass;        // passes with a shared list (selects its length word); grid path: chunks listed
     int consumed[4];  // prod value seen when the sub-image's pass last ran
 };
 
@@ -307,6 +312,15 @@ __device__ __forceinline__ void activate_pixel(const Img<LDS>& g, int i, int j, 
     __hip_atomic_fetch_or(g.M + q, 1u << (c & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     g.D[q] = 1;
     g.ctl[CTL_PROD + (i & 1) * 2 + (j & 1)] = serial;
+}
+
+// Orders the stores a wave made before it against the loads its lanes make
+// after it (a wave-private list written by some lanes and read by others).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // exclusive prefix over the wave of v in [0, 7]; *total = sum over the wave.
@@ -477,6 +491,9 @@ __device__ __forceinline__ bool test_word(const PassPtrs<LDS>& p, int idx, int r
 // the other three, so flags need no atomics. A pass first collects its
 // flagged live words into a list (4 flags per thread per load), then tests
 // the list densely; a pass whose sub-image has no flagged word is skipped.
+// A sub-image of at most 2 NT words is instead split into one 128-word chunk
+// per wave, and each wave lists and tests its own chunk's words, which saves
+// the workgroup barrier between listing and testing.
 // NT: the workgroup size (threads) the caller is launched with.
 template <bool LDS, int NT = BLOCK>
 __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& sc)
@@ -503,71 +520,127 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
             const auto Ds = g.D + g.sub(si, sj);
             const int rows = (g.H - si + 1) >> 1;
             const int nw = rows * WW;
-            lds_i32* cnt = lcnt + (sc.npass & 1);
-            // collect: flagged words whose activated candidates are still live;
-            // every lane runs the same number of iterations (wave-wide prefix).
-            // The four words' M and S are loaded with their flags, flagged or
-            // not, so the live test waits for one round trip, not three (b0 is
-            // a multiple of 4 below nw <= SUB, and SUB is a multiple of 4, so
-            // the four words lie in the sub-image)
-            using U4 = typename std::conditional<LDS, const lds_u4*, const glb_u4*>::type;
-            const int niter = (nw + 4 * NT - 1) / (4 * NT);
-            for (int it = 0; it < niter; ++it) {
-                const int b0 = 4 * threadIdx.x + it * 4 * NT;
-                unsigned f4 = 0;
-                u32x4 m4 = {0u, 0u, 0u, 0u}, s4 = m4;
+            const PassPtrs<LDS> pp = pass_ptrs(g, si, sj);
+            bool changed_here = false;
+            if (nw <= 2 * NT) {
+                // one chunk of 128 words per wave, listed at L[w0 ..] and
+                // tested by the same wave: a test writes only its own word of
+                // S and flags of the other three sub-images, and a wave's
+                // listing reads only its own chunk's flags, M and S, so no
+                // workgroup barrier is needed between them. The two words'
+                // M and S are loaded with their flags (b0 is even and below
+                // nw <= SUB, a multiple of 4, so both words lie in the
+                // sub-image); the list holds at most the chunk's words below
+                // nw.
+                using U2 = typename std::conditional<LDS, const lds_u2*, const glb_u2*>::type;
+                using F2 = typename std::conditional<LDS, lds_u16*, glb_u16*>::type;
+                const int lane = (int)(threadIdx.x & 63);
+                const int w0 = 2 * (int)(threadIdx.x & ~63u);
+                const int b0 = w0 + 2 * lane;
+                unsigned f2 = 0;
+                u32x2 m2 = {0u, 0u}, s2 = m2;
                 if (b0 < nw) {
-                    f4 = *(const typename std::conditional<LDS, lds_u32*, glb_u32*>::type)(Ds + b0);
-                    m4 = *(U4)(Ms + b0);
-                    s4 = *(U4)(Ss + b0);
+                    f2 = *(F2)(Ds + b0);
+                    m2 = *(U2)(Ms + b0);
+                    s2 = *(U2)(Ss + b0);
                 }
-                const uint32_t live[4] = {m4.x & (s4.x ^ flip), m4.y & (s4.y ^ flip), m4.z & (s4.z ^ flip),
-                                          m4.w & (s4.w ^ flip)};
                 unsigned nl = 0;
-                int q0 = 0, q1 = 0, q2 = 0, q3 = 0;
-                if (f4) {
-                    *(typename std::conditional<LDS, lds_u32*, glb_u32*>::type)(Ds + b0) = 0u;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int q = b0 + j;
-                        if (((f4 >> (8 * j)) & 0xFFu) && q < nw && live[j]) {
-                            if (nl == 0) q0 = q;
-                            else if (nl == 1) q1 = q;
-                            else if (nl == 2) q2 = q;
-                            else q3 = q;
-                            ++nl;
-                        }
+                int q0 = 0, q1 = 0;
+                if (f2) {
+                    *(F2)(Ds + b0) = (uint16_t)0;
+                    if ((f2 & 0xFFu) && (m2.x & (s2.x ^ flip))) {
+                        q0 = b0;
+                        nl = 1;
+                    }
+                    if ((f2 >> 8) && b0 + 1 < nw && (m2.y & (s2.y ^ flip))) {
+                        if (nl) q1 = b0 + 1;
+                        else q0 = b0 + 1;
+                        ++nl;
                     }
                 }
                 unsigned tot;
                 const unsigned off = wave_prefix(nl, &tot);
-                unsigned base = 0;
                 if (tot) {
-                    if ((threadIdx.x & 63) == 0)
-                        base = (unsigned)__hip_atomic_fetch_add(cnt, (int)tot, __ATOMIC_RELAXED,
-                                                                __HIP_MEMORY_SCOPE_WORKGROUP);
-                    base = (unsigned)__builtin_amdgcn_readfirstlane((int)base) + off;
-                    if (nl > 0) g.L[base] = q0;
-                    if (nl > 1) g.L[base + 1] = q1;
-                    if (nl > 2) g.L[base + 2] = q2;
-                    if (nl > 3) g.L[base + 3] = q3;
+                    const auto Lw = g.L + w0;
+                    if (nl > 0) Lw[off] = q0;
+                    if (nl > 1) Lw[off + 1] = q1;
+                    wave_sync();
+                    for (int t = lane; t < (int)tot; t += 64) {
+                        const int idx = (int)Lw[t];
+                        int rr = (int)((float)idx * invWW);
+                        if (rr * WW > idx)
+                            --rr;
+                        else if ((rr + 1) * WW <= idx)
+                            ++rr;
+                        changed_here |= test_word(pp, idx, rr, si, sj, WW, g.H, flip, g.conn4);
+                    }
                 }
-            }
-            __syncthreads();
-            if (threadIdx.x == 0)
-                lcnt[(sc.npass + 1) & 1] = 0;  // every thread read it one pass ago
-            const int n = *cnt;
-            // test the listed words
-            const PassPtrs<LDS> pp = pass_ptrs(g, si, sj);
-            bool changed_here = false;
-            for (int t = threadIdx.x; t < n; t += NT) {
-                const int idx = (int)g.L[t];
-                int rr = (int)((float)idx * invWW);
-                if (rr * WW > idx)
-                    --rr;
-                else if ((rr + 1) * WW <= idx)
-                    ++rr;
-                changed_here |= test_word(pp, idx, rr, si, sj, WW, g.H, flip, g.conn4);
+            } else {
+                lds_i32* cnt = lcnt + (sc.npass & 1);
+                // collect: flagged words whose activated candidates are still live;
+                // every lane runs the same number of iterations (wave-wide prefix).
+                // The four words' M and S are loaded with their flags, flagged or
+                // not, so the live test waits for one round trip, not three (b0 is
+                // a multiple of 4 below nw <= SUB, and SUB is a multiple of 4, so
+                // the four words lie in the sub-image)
+                using U4 = typename std::conditional<LDS, const lds_u4*, const glb_u4*>::type;
+                const int niter = (nw + 4 * NT - 1) / (4 * NT);
+                for (int it = 0; it < niter; ++it) {
+                    const int b0 = 4 * threadIdx.x + it * 4 * NT;
+                    unsigned f4 = 0;
+                    u32x4 m4 = {0u, 0u, 0u, 0u}, s4 = m4;
+                    if (b0 < nw) {
+                        f4 = *(const typename std::conditional<LDS, lds_u32*, glb_u32*>::type)(Ds + b0);
+                        m4 = *(U4)(Ms + b0);
+                        s4 = *(U4)(Ss + b0);
+                    }
+                    const uint32_t live[4] = {m4.x & (s4.x ^ flip), m4.y & (s4.y ^ flip), m4.z & (s4.z ^ flip),
+                                              m4.w & (s4.w ^ flip)};
+                    unsigned nl = 0;
+                    int q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+                    if (f4) {
+                        *(typename std::conditional<LDS, lds_u32*, glb_u32*>::type)(Ds + b0) = 0u;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int q = b0 + j;
+                            if (((f4 >> (8 * j)) & 0xFFu) && q < nw && live[j]) {
+                                if (nl == 0) q0 = q;
+                                else if (nl == 1) q1 = q;
+                                else if (nl == 2) q2 = q;
+                                else q3 = q;
+                                ++nl;
+                            }
+                        }
+                    }
+                    unsigned tot;
+                    const unsigned off = wave_prefix(nl, &tot);
+                    unsigned base = 0;
+                    if (tot) {
+                        if ((threadIdx.x & 63) == 0)
+                            base = (unsigned)__hip_atomic_fetch_add(cnt, (int)tot, __ATOMIC_RELAXED,
+                                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+                        base = (unsigned)__builtin_amdgcn_readfirstlane((int)base) + off;
+                        if (nl > 0) g.L[base] = q0;
+                        if (nl > 1) g.L[base + 1] = q1;
+                        if (nl > 2) g.L[base + 2] = q2;
+                        if (nl > 3) g.L[base + 3] = q3;
+                    }
+                }
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    lcnt[(sc.npass + 1) & 1] = 0;  // every thread read it one pass ago
+                const int n = *cnt;
+                // test the listed words
+                for (int t = threadIdx.x; t < n; t += NT) {
+                    const int idx = (int)g.L[t];
+                    int rr = (int)((float)idx * invWW);
+                    if (rr * WW > idx)
+                        --rr;
+                    else if ((rr + 1) * WW <= idx)
+                        ++rr;
+                    changed_here |= test_word(pp, idx, rr, si, sj, WW, g.H, flip, g.conn4);
+                }
+                ++sc.npass;
             }
             // one lane per wave records the change (a same-address store from
             // many lanes would be serialised)
@@ -583,7 +656,6 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
                 }
             }
             __syncthreads();
-            ++sc.npass;
         }
         // a round changed nothing (and the level is done) iff no pass of it
         // stored its serial in chg; a round without any pass changes nothing
