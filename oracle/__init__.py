@@ -205,3 +205,12 @@ def hasf(X, C, r: int, stages: bool = False, queue: bool = False, D=None, n: int
         d, dp = _opt_u8(D)
         _check(_load().oracle_hasf_cd(x.ctypes.data_as(U8P), cp, dp, H, W, r, n, sp), "hasf_cd")
     return (x, st[:r]) if stages else x
+
+
+def hasf_labels(Lab, values, r: int):
+    """Per-label smoothing: for each label value v, HASF of order r (C and D
+    empty, (8,4), cutting first) of the object set {p : Lab[p] == v}, as its
+    own binary image (Sec. 2 applied label by label). Returns an (n, H, W)
+    array of 0/1 planes, one per value, in the order given."""
+    lab = np.ascontiguousarray(Lab, dtype=np.uint8)
+    return np.stack([hasf((lab == np.uint8(v)).astype(np.uint8), None, r) for v in values])
