@@ -206,6 +206,29 @@ typedef struct {
 hasf_status hasf_filter_batch(hasf_ctx* ctx, const hasf_image* imgs, int n);
 
 /*
+ * Per-label smoothing of a label (grey-level) image: the binary method of
+ * Sec. 2 applied to each label as its own object set (Sec. 3.1 places
+ * grey-level topological operators in the same class; the paper smooths
+ * binary sets only). For k in [0, n), X_k = {p : L[p] == values[k]}
+ * is filtered as hasf_filter(X_k, C = empty, r) -- (8,4), cutting first --
+ * and written as 0/1 to plane k of out. The n planes are extracted by one
+ * kernel and filtered in one batch (as hasf_filter_batch). The planes are
+ * smoothed independently: they may overlap or leave pixels uncovered, and
+ * no label image is rebuilt from them.
+ *   L       device, H rows of ld bytes (read only)
+ *   values  host array of n label values, no value twice; 1 <= n <= 256
+ *   out     device; plane k starts at out + k * plane_stride and has H rows
+ *           of ld_out bytes (ld_out >= W, plane_stride >= (H - 1) * ld_out + W,
+ *           so planes do not overlap); it must not overlap L
+ * HASF_EINVAL (before any device work) for NULL pointers, sizes as in
+ * hasf_filter, n outside [1, 256], a repeated value, r outside
+ * [0, HASF_R_MAX], a short ld_out or plane_stride, or out overlapping L.
+ */
+hasf_status hasf_filter_labels(hasf_ctx* ctx, const uint8_t* L, int H, int W, int64_t ld,
+                               const uint8_t* values, int n, int r, uint8_t* out, int64_t ld_out,
+                               int64_t plane_stride);
+
+/*
  * Served stream (continuous batching). hasf_serve starts a server on ctx's
  * device: a host dispatcher thread and a few launch lanes (streams of their
  * own, each with at most one launch of the batched filter kernel in flight).

@@ -574,6 +574,99 @@ hasf_status hasf_filter_batch(hasf_ctx* ctx, const hasf_image* imgs, int n)
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// per-label smoothing
+// ---------------------------------------------------------------------------
+namespace {
+
+struct LabelValues {
+    uint8_t v[256];
+};
+
+// plane k of out = (L == v[k]) as 0/1: one thread per pixel of a row (y: row)
+__global__ __launch_bounds__(256) void labels_to_planes(const uint8_t* __restrict__ L, long long ld, int W,
+                                                       LabelValues vals, int n, uint8_t* __restrict__ out,
+                                                       long long ld_out, long long stride)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= W)
+        return;
+    const uint8_t l = L[(long long)i * ld + j];
+    uint8_t* o = out + (long long)i * ld_out + j;
+    for (int k = 0; k < n; ++k)
+        o[(long long)k * stride] = l == vals.v[k] ? 1 : 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+hasf_status hasf_filter_labels(hasf_ctx* ctx, const uint8_t* L, int H, int W, int64_t ld, const uint8_t* values,
+                               int n, int r, uint8_t* out, int64_t ld_out, int64_t plane_stride)
+{
+    const char* what = "hasf_filter_labels";
+    hasf_status s = check_image(ctx, L, H, W, ld, what);
+    if (s)
+        return s;
+    if (!values || !out) {
+        set_err(ctx, "%s: values and out must not be NULL", what);
+        return HASF_EINVAL;
+    }
+    if (n < 1 || n > 256) {
+        set_err(ctx, "%s: n = %d outside [1, 256]", what, n);
+        return HASF_EINVAL;
+    }
+    if (r < 0 || r > HASF_R_MAX) {
+        set_err(ctx, "%s: r = %d outside [0, %d]", what, r, HASF_R_MAX);
+        return HASF_EINVAL;
+    }
+    const int64_t plane = (int64_t)(H - 1) * ld_out + W;  // bytes a plane spans
+    if (ld_out < W || plane_stride < plane) {
+        set_err(ctx, "%s: need ld_out >= W and plane_stride >= (H - 1) * ld_out + W (got %lld, %lld)", what,
+                (long long)ld_out, (long long)plane_stride);
+        return HASF_EINVAL;
+    }
+    bool seen[256] = {};
+    LabelValues vals{};
+    for (int k = 0; k < n; ++k) {
+        if (seen[values[k]]) {
+            set_err(ctx, "%s: label value %d given twice", what, (int)values[k]);
+            return HASF_EINVAL;
+        }
+        seen[values[k]] = true;
+        vals.v[k] = values[k];
+    }
+    const uintptr_t l0 = (uintptr_t)L, l1 = l0 + (uintptr_t)((int64_t)(H - 1) * ld + W);
+    const uintptr_t o0 = (uintptr_t)out, o1 = o0 + (uintptr_t)((int64_t)(n - 1) * plane_stride + plane);
+    if (o0 < l1 && l0 < o1) {
+        set_err(ctx, "%s: out overlaps L", what);
+        return HASF_EINVAL;
+    }
+    hipSetDevice(ctx->device);
+    hipLaunchKernelGGL(labels_to_planes, dim3((W + 255) / 256, H), dim3(256), 0, ctx->stream, L, (long long)ld, W,
+                       vals, n, out, (long long)ld_out, (long long)plane_stride);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "labels_to_planes launch");
+    std::vector<hasf_image> imgs(n);
+    for (int k = 0; k < n; ++k) {
+        hasf_image& im = imgs[k];
+        im.X = out + (int64_t)k * plane_stride;
+        im.C = nullptr;
+        im.H = H;
+        im.W = W;
+        im.ld = ld_out;
+        im.r = r;
+        im.D = nullptr;
+        im.conn = 8;
+        im.order = 0;
+    }
+    return run_images(ctx, imgs.data(), n, what);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
 // standalone thinning / thickening
 // ---------------------------------------------------------------------------
 namespace {

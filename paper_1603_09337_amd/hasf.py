@@ -93,10 +93,13 @@ _lib.hasf_filter.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c
 _lib.hasf_filter_cd.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
                                 ctypes.c_int]
 _lib.hasf_filter_batch.argtypes = [_vp, ctypes.POINTER(_Image), ctypes.c_int]
+_lib.hasf_filter_labels.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                    ctypes.POINTER(ctypes.c_uint8), ctypes.c_int, ctypes.c_int, _vp,
+                                    ctypes.c_int64, ctypes.c_int64]
 for _f in ("hasf_create", "hasf_set_stream", "hasf_sync", "hasf_simple_lut", "hasf_edt_sq",
            "hasf_homotopic_thin", "hasf_homotopic_thicken", "hasf_homotopic_thin_conn",
            "hasf_homotopic_thicken_conn", "hasf_filter", "hasf_filter_cd",
-           "hasf_filter_batch"):
+           "hasf_filter_batch", "hasf_filter_labels"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -267,6 +270,26 @@ class Context:
         self._stream()
         self._check(_lib.hasf_filter_batch(self._h, arr, len(items)))
         return [it[0] for it in items]
+
+    def filter_labels(self, L, values, r: int = 1, out=None):
+        """hasf_filter_labels: plane k of the result is HASF of order r of the
+        pixels of L equal to values[k], as 0/1. out: None (an (n, H, W) uint8
+        tensor is allocated) or an (n, H, W) uint8 CUDA tensor with unit column
+        stride whose planes do not overlap."""
+        H, W, ld = _img(L, "L", self.device)
+        vals = bytes(int(v) for v in values)  # ValueError outside 0..255
+        n = len(vals)
+        if out is None:
+            out = self._torch.empty((max(n, 1), H, W), dtype=self._torch.uint8, device=L.device)
+        elif (out.dtype != self._torch.uint8 or out.dim() != 3 or tuple(out.shape) != (n, H, W)
+              or out.stride(2) != 1 or not out.is_cuda or out.device.index != self.device):
+            raise ValueError("out must be an (n, H, W) uint8 tensor with unit column stride on cuda:%d"
+                             % self.device)
+        buf = (ctypes.c_uint8 * max(n, 1)).from_buffer_copy(vals if n else b"\0")
+        self._stream()
+        self._check(_lib.hasf_filter_labels(self._h, _ptr(L), H, W, ld, buf, n, r, _ptr(out), out.stride(1),
+                                            out.stride(0)))
+        return out
 
 
 class Server:

@@ -193,3 +193,27 @@ def random_binary(H, W, density, seed):
     """Plain Bernoulli image, for edge cases and brute-force checks."""
     rng = _rng(seed)
     return (rng.random((H, W)) < density).astype(np.uint8)
+
+
+def label_image(H, W, n_labels, seed, n_sites=None, noise=0.01):
+    """Label image for the per-label filter: the nearest of n_sites random
+    sites (squared distance, ties to the lower site) gives each pixel one of
+    n_labels values 0..n_labels-1 (drawn per site), then a fraction `noise`
+    of the pixels takes a random label."""
+    rng = _rng(seed)
+    n_sites = n_sites or 3 * n_labels
+    sy = rng.integers(0, H, n_sites)
+    sx = rng.integers(0, W, n_sites)
+    lab_of = rng.integers(0, n_labels, n_sites).astype(np.uint8)
+    ii = np.arange(H)[:, None]
+    jj = np.arange(W)[None, :]
+    best = np.full((H, W), np.iinfo(np.int64).max, np.int64)
+    out = np.zeros((H, W), np.uint8)
+    for k in range(n_sites):
+        d = (ii - sy[k]) ** 2 + (jj - sx[k]) ** 2
+        m = d < best
+        best[m] = d[m]
+        out[m] = lab_of[k]
+    flip = rng.random((H, W)) < noise
+    out[flip] = rng.integers(0, n_labels, int(flip.sum())).astype(np.uint8)
+    return out
