@@ -223,6 +223,7 @@ hasf_status hasf_filter_batch(hasf_ctx* ctx, const hasf_image* imgs, int n);
  * HASF_EINVAL (before any device work) for NULL pointers, sizes as in
  * hasf_filter, n outside [1, 256], a repeated value, r outside
  * [0, HASF_R_MAX], a short ld_out or plane_stride, or out overlapping L.
+ * On a later failure (HASF_ENOMEM, HASF_EDEVICE) the planes are undefined.
  */
 hasf_status hasf_filter_labels(hasf_ctx* ctx, const uint8_t* L, int H, int W, int64_t ld,
                                const uint8_t* values, int n, int r, uint8_t* out, int64_t ld_out,
