@@ -380,19 +380,31 @@ __device__ __forceinline__ WordNbhd load_word(const PassPtrs<LDS>& p, int idx, i
     n.hasS = row + 1 < H;
     n.iN = (si ? rr : rr - 1) * WW + my_w;  // row - 1 in the other parity
     n.iS = (si ? rr + 1 : rr) * WW + my_w;  // row + 1
+    // Every load is issued, at an index inside the sub-image (a missing
+    // neighbour row or column reads the word's own index, or its row), and a
+    // missing neighbour's value is then replaced by 0: no branch per load.
+    // iN and iS themselves become such indices (apply_word flags through
+    // them: a flag on a word whose inputs did not change only re-tests it).
+    const int l = n.hasL ? 1 : 0, r = n.hasR ? 1 : 0;
+    n.iN = n.hasN ? n.iN : (n.hasS ? n.iS : idx);
+    n.iS = n.hasS ? n.iS : n.iN;
+    const uint32_t xl = p.Sx[idx - l], xr = p.Sx[idx + r];
+    const uint32_t nn = p.Sy[n.iN], sv = p.Sy[n.iS];
+    const uint32_t nc = p.Sxy[n.iN], nl = p.Sxy[n.iN - l], nr = p.Sxy[n.iN + r];
+    const uint32_t dc = p.Sxy[n.iS], dl = p.Sxy[n.iS - l], dr = p.Sxy[n.iS + r];
     n.scw = p.Ss[idx];
     n.m = p.Ms[idx];
     n.xc = p.Sx[idx];
-    n.xl = n.hasL ? p.Sx[idx - 1] : 0u;
-    n.xr = n.hasR ? p.Sx[idx + 1] : 0u;
-    n.nn = n.hasN ? p.Sy[n.iN] : 0u;
-    n.sv = n.hasS ? p.Sy[n.iS] : 0u;
-    n.nc = n.hasN ? p.Sxy[n.iN] : 0u;
-    n.nl = n.hasN && n.hasL ? p.Sxy[n.iN - 1] : 0u;
-    n.nr = n.hasN && n.hasR ? p.Sxy[n.iN + 1] : 0u;
-    n.dc = n.hasS ? p.Sxy[n.iS] : 0u;
-    n.dl = n.hasS && n.hasL ? p.Sxy[n.iS - 1] : 0u;
-    n.dr = n.hasS && n.hasR ? p.Sxy[n.iS + 1] : 0u;
+    n.xl = n.hasL ? xl : 0u;
+    n.xr = n.hasR ? xr : 0u;
+    n.nn = n.hasN ? nn : 0u;
+    n.sv = n.hasS ? sv : 0u;
+    n.nc = n.hasN ? nc : 0u;
+    n.nl = n.hasN && n.hasL ? nl : 0u;
+    n.nr = n.hasN && n.hasR ? nr : 0u;
+    n.dc = n.hasS ? dc : 0u;
+    n.dl = n.hasS && n.hasL ? dl : 0u;
+    n.dr = n.hasS && n.hasR ? dr : 0u;
     return n;
 }
 
@@ -439,29 +451,23 @@ __device__ __forceinline__ bool apply_word(const PassPtrs<LDS>& p, const WordNbh
     const uint32_t del = live & simple_bits<uint32_t>(e, ne, nn, nw2, w, sw, sv, se);
     if (!del)
         return false;
+    // the words that read this one, flagged without branches: a missing
+    // neighbour column or row maps to a word flagged anyway (load_word), or,
+    // for a one-row image, to a word of an empty sub-image
     const int idx = n.idx, iN = n.iN, iS = n.iS;
+    const int l = n.hasL ? 1 : 0, r = n.hasR ? 1 : 0;
     p.Ss[idx] = n.scw ^ del;
     p.Dx[idx] = 1;
-    if (n.hasL)
-        p.Dx[idx - 1] = 1;
-    if (n.hasR)
-        p.Dx[idx + 1] = 1;
-    if (n.hasN) {
-        p.Dy[iN] = 1;
-        p.Dxy[iN] = 1;
-        if (n.hasL)
-            p.Dxy[iN - 1] = 1;
-        if (n.hasR)
-            p.Dxy[iN + 1] = 1;
-    }
-    if (n.hasS) {
-        p.Dy[iS] = 1;
-        p.Dxy[iS] = 1;
-        if (n.hasL)
-            p.Dxy[iS - 1] = 1;
-        if (n.hasR)
-            p.Dxy[iS + 1] = 1;
-    }
+    p.Dx[idx - l] = 1;
+    p.Dx[idx + r] = 1;
+    p.Dy[iN] = 1;
+    p.Dxy[iN] = 1;
+    p.Dxy[iN - l] = 1;
+    p.Dxy[iN + r] = 1;
+    p.Dy[iS] = 1;
+    p.Dxy[iS] = 1;
+    p.Dxy[iS - l] = 1;
+    p.Dxy[iS + r] = 1;
     return true;
 }
 
