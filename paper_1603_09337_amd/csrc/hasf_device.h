@@ -600,24 +600,18 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
                         m4 = *(U4)(Ms + b0);
                         s4 = *(U4)(Ss + b0);
                     }
-                    const uint32_t live[4] = {m4.x & (s4.x ^ flip), m4.y & (s4.y ^ flip), m4.z & (s4.z ^ flip),
-                                              m4.w & (s4.w ^ flip)};
-                    unsigned nl = 0;
-                    int q0 = 0, q1 = 0, q2 = 0, q3 = 0;
-                    if (f4) {
+                    // bit j of keep: word b0 + j is flagged, inside the
+                    // sub-image and has live candidates
+                    const int rem = nw - b0;
+                    const uint32_t inside = rem >= 4 ? 0xFu : (rem > 0 ? (1u << rem) - 1u : 0u);
+                    const uint32_t lv = (uint32_t)((m4.x & (s4.x ^ flip)) != 0u) |
+                                        ((uint32_t)((m4.y & (s4.y ^ flip)) != 0u) << 1) |
+                                        ((uint32_t)((m4.z & (s4.z ^ flip)) != 0u) << 2) |
+                                        ((uint32_t)((m4.w & (s4.w ^ flip)) != 0u) << 3);
+                    const uint32_t keep = nz4(f4) & inside & lv;
+                    if (f4)
                         *(typename std::conditional<LDS, lds_u32*, glb_u32*>::type)(Ds + b0) = 0u;
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const int q = b0 + j;
-                            if (((f4 >> (8 * j)) & 0xFFu) && q < nw && live[j]) {
-                                if (nl == 0) q0 = q;
-                                else if (nl == 1) q1 = q;
-                                else if (nl == 2) q2 = q;
-                                else q3 = q;
-                                ++nl;
-                            }
-                        }
-                    }
+                    const unsigned nl = (unsigned)__popc(keep);
                     unsigned tot;
                     const unsigned off = wave_prefix(nl, &tot);
                     unsigned base = 0;
@@ -626,10 +620,21 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
                             base = (unsigned)__hip_atomic_fetch_add(cnt, (int)tot, __ATOMIC_RELAXED,
                                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
                         base = (unsigned)__builtin_amdgcn_readfirstlane((int)base) + off;
-                        if (nl > 0) g.L[base] = q0;
-                        if (nl > 1) g.L[base + 1] = q1;
-                        if (nl > 2) g.L[base + 2] = q2;
-                        if (nl > 3) g.L[base + 3] = q3;
+                        if (nl) {
+                            // the k-th listed word is the k-th set bit of keep;
+                            // entries past nl rewrite the last one with the
+                            // same value, so the four stores need no branch
+                            const uint32_t k1 = keep & (keep - 1u), k2 = k1 & (k1 - 1u), k3 = k2 & (k2 - 1u);
+                            const int j0 = __ffs(keep) - 1;
+                            const int j1 = k1 ? __ffs(k1) - 1 : j0;
+                            const int j2 = k2 ? __ffs(k2) - 1 : j1;
+                            const int j3 = k3 ? __ffs(k3) - 1 : j2;
+                            const unsigned last = nl - 1u;
+                            g.L[base] = b0 + j0;
+                            g.L[base + min(1u, last)] = b0 + j1;
+                            g.L[base + min(2u, last)] = b0 + j2;
+                            g.L[base + min(3u, last)] = b0 + j3;
+                        }
                     }
                 }
                 __syncthreads();
