@@ -506,6 +506,23 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
 {
     const int WW = g.WW;
     const float invWW = 1.0f / (float)WW;
+    // row of a word index: in LDS (index < 2^16, WW <= 1024) a multiply by
+    // ceil(2^32 / WW) taking the high half is exact (WW = 1, whose factor does
+    // not fit 32 bits, is the index itself); in global memory the float
+    // estimate is corrected by one step either way
+    const uint32_t magic = 0xFFFFFFFFu / (uint32_t)WW + 1u;
+    auto row_of = [&](int idx) {
+        if constexpr (LDS) {
+            return WW == 1 ? idx : (int)__umulhi((uint32_t)idx, magic);
+        } else {
+            int rr = (int)((float)idx * invWW);
+            if (rr * WW > idx)
+                --rr;
+            else if ((rr + 1) * WW <= idx)
+                ++rr;
+            return rr;
+        }
+    };
     const uint32_t flip = thin ? 0u : ~0u;  // live = M & (S ^ flip)
     lds_i32* chg = g.ctl + CTL_CHG;
     lds_i32* lcnt = g.ctl + CTL_CNT;
@@ -573,12 +590,7 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
                     wave_sync();
                     for (int t = lane; t < (int)tot; t += 64) {
                         const int idx = (int)Lw[t];
-                        int rr = (int)((float)idx * invWW);
-                        if (rr * WW > idx)
-                            --rr;
-                        else if ((rr + 1) * WW <= idx)
-                            ++rr;
-                        changed_here |= test_word(pp, idx, rr, si, sj, WW, g.H, flip, g.conn4);
+                        changed_here |= test_word(pp, idx, row_of(idx), si, sj, WW, g.H, flip, g.conn4);
                     }
                 }
             } else {
@@ -644,12 +656,7 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
                 // test the listed words
                 for (int t = threadIdx.x; t < n; t += NT) {
                     const int idx = (int)g.L[t];
-                    int rr = (int)((float)idx * invWW);
-                    if (rr * WW > idx)
-                        --rr;
-                    else if ((rr + 1) * WW <= idx)
-                        ++rr;
-                    changed_here |= test_word(pp, idx, rr, si, sj, WW, g.H, flip, g.conn4);
+                    changed_here |= test_word(pp, idx, row_of(idx), si, sj, WW, g.H, flip, g.conn4);
                 }
                 ++sc.npass;
             }
