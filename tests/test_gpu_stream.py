@@ -83,6 +83,22 @@ def test_frames_arriving_during_launches_overlap():
         assert np.array_equal(got[k], oracle.hasf(X, C, r)), "frame %d vs oracle" % k
 
 
+def test_all_lanes_in_use():
+    # the largest lane count (the benchmark's): frames spread over 16 lanes
+    frames = _frames(48, 128, 320, 23, rmax=5)
+    srv = hasf.Server(ctx(), pool_bytes=256 << 20, lanes=hasf.HASF_SERVE_LANES_MAX)
+    say("stream 48 over %d lanes" % hasf.HASF_SERVE_LANES_MAX)
+    got, res = _run(srv, frames, gap_s=0.0002)
+    st = srv.stats()
+    srv.stop()
+    assert st["completed"] == 48 and st["kernel_launches"] >= 2
+    for k, ((X, C, r), g) in enumerate(zip(frames, got)):
+        assert np.array_equal(g, _alone(X, C, r)), "frame %d" % k
+    for k in range(0, 48, 8):
+        X, C, r = frames[k]
+        assert np.array_equal(got[k], oracle.hasf(X, C, r)), "frame %d vs oracle" % k
+
+
 def test_small_frames_finish_before_a_large_one():
     # one lane, no grid path: a blocker keeps the lane busy while the large and
     # the small frames are submitted, so all of them share the next launch;
