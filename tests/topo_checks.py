@@ -234,3 +234,116 @@ def global_simple48(m: int) -> bool:
     after_o = ndimage.label(img, FOUR)[1]
     after_b = ndimage.label(1 - img, EIGHT)[1]
     return before_o == after_o and before_b == after_b
+
+
+# ---------------------------------------------------------------------------
+# An independent composition of the cutting HC_i and the filling HF_i (Sec. 2,
+# eq. (i) and eq. (ii)) from parts that share nothing with the oracle: ball
+# stamping for the thresholds, scipy's exact Euclidean transform (nearest
+# feature indices, squared distances in integers) for the priorities, and a
+# numpy subfield schedule. It fixes which distance map orders each of the four
+# thinnings and thickenings of a radius:
+#   HC thinning    priority d^2(., complement of X u outside)
+#   HC thickening  priority d^2(., Y), Y the thinned set
+#   HF thickening  priority d^2(., X)
+#   HF thinning    priority d^2(., complement of Z u outside), Z the thickened set
+# ---------------------------------------------------------------------------
+def edt_sq_lib(F: np.ndarray, frame: bool) -> np.ndarray:
+    """Squared distance to the nearest nonzero pixel of F (with frame: or to
+    any pixel outside the window), from scipy's exact transform: the nearest
+    feature's indices give the distance in integers."""
+    H, W = F.shape
+    if frame:
+        G = np.ones((H + 2, W + 2), dtype=bool)
+        G[1:-1, 1:-1] = F != 0
+        off = 1
+    else:
+        G = F != 0
+        off = 0
+    if not G.any():
+        return np.full((H, W), np.iinfo(np.uint32).max, dtype=np.uint32)
+    _, ind = ndimage.distance_transform_edt(~G, return_indices=True)
+    ii, jj = np.mgrid[0:G.shape[0], 0:G.shape[1]]
+    d2 = (ii - ind[0]) ** 2 + (jj - ind[1]) ** 2
+    return d2[off:off + H, off:off + W].astype(np.uint32)
+
+
+def schedule_np(mode: int, S: np.ndarray, B, P: np.ndarray, table) -> np.ndarray:
+    """The distance-ordered subfield schedule with whole-subfield numpy passes:
+    levels = distinct P over the candidates, ascending; at level d, rounds of
+    the passes (even,even) (even,odd) (odd,even) (odd,odd) over the points with
+    P <= d until a round changes nothing. mode 0 deletes simple points of
+    S \\ B, mode 1 adds simple points of B \\ S."""
+    S = (np.asarray(S) != 0).astype(np.uint8).copy()
+    H, W = S.shape
+    Bm = np.zeros((H, W), dtype=bool) if B is None else (np.asarray(B) != 0)
+    tab = np.asarray(table, dtype=bool)
+    cand = (S == 1) & ~Bm if mode == 0 else (S == 0) & Bm
+    ii, jj = np.mgrid[0:H, 0:W]
+    par = [((ii % 2) == si) & ((jj % 2) == sj) for si, sj in ((0, 0), (0, 1), (1, 0), (1, 1))]
+    for d in np.unique(P[cand]):
+        act = P <= d
+        while True:
+            changed = False
+            for sub in par:
+                ok = tab[neighbourhood_codes(S)]
+                if mode == 0:
+                    hit = sub & act & (S == 1) & ~Bm & ok
+                else:
+                    hit = sub & act & (S == 0) & Bm & ok
+                if hit.any():
+                    S[hit] = mode
+                    changed = True
+            if not changed:
+                break
+    return S
+
+
+def simple_table(n: int = 8):
+    return [global_simple(m) if n == 8 else global_simple48(m) for m in range(256)]
+
+
+def hc_composed(X, C, i: int, table):
+    """HC_i (eq. (i)): Y = H(X, eps_i(X) u C) ordered by d^2 to the background
+    (outside included); X' = *H(Y, delta_i(Y) n X) ordered by d^2 to Y.
+    Returns (Y, X')."""
+    X = (np.asarray(X) != 0).astype(np.uint8)
+    K = erode_stamp(X, i) | (np.zeros(X.shape, bool) if C is None else (np.asarray(C) != 0))
+    Y = schedule_np(0, X, K, edt_sq_lib(X == 0, True), table)
+    V = dilate_stamp(Y, i) & (X != 0)
+    return Y, schedule_np(1, Y, V, edt_sq_lib(Y, False), table)
+
+
+def hf_composed(X, D, i: int, table):
+    """HF_i (eq. (ii), W read as eps_i(Z) u X): Z = *H(X, delta_i(X) \\ D)
+    ordered by d^2 to X; X' = H(Z, eps_i(Z) u X) ordered by d^2 to the
+    background of Z (outside included). Returns (Z, X')."""
+    X = (np.asarray(X) != 0).astype(np.uint8)
+    L = dilate_stamp(X, i) & ~(np.zeros(X.shape, bool) if D is None else (np.asarray(D) != 0))
+    Z = schedule_np(1, X, L, edt_sq_lib(X, False), table)
+    Wc = erode_stamp(Z, i) | (X != 0)
+    return Z, schedule_np(0, Z, Wc, edt_sq_lib(Z == 0, True), table)
+
+
+def hasf_composed(X, C, D, r: int, n: int = 8, order: int = 0):
+    """HASF of order r from the parts above: per radius HC_i then HF_i (order
+    0) or HF_i then HC_i (order 1), with C <- C n X and D <- D \\ X taken from
+    the input. Returns an (r, 4, H, W) array of the states in the order they
+    are produced (thinned, cut, thickened, filled for order 0)."""
+    X = (np.asarray(X) != 0).astype(np.uint8)
+    Cn = None if C is None else ((np.asarray(C) != 0) & (X != 0))
+    Dn = None if D is None else ((np.asarray(D) != 0) & (X == 0))
+    table = simple_table(n)
+    out = []
+    x = X
+    for i in range(1, r + 1):
+        st = []
+        ops = (("c", "f") if order == 0 else ("f", "c"))
+        for op in ops:
+            if op == "c":
+                a, x = hc_composed(x, Cn, i, table)
+            else:
+                a, x = hf_composed(x, Dn, i, table)
+            st += [a, x]
+        out.append(np.stack(st))
+    return np.stack(out) if out else np.zeros((0, 4) + X.shape, np.uint8)
