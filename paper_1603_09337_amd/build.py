@@ -4,6 +4,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -12,7 +13,7 @@ OUT = os.path.join(HERE, "_lib", "libhasf.so")
 SOURCES = ["hasf_api.hip", "hasf_filter.hip", "hasf_edt.hip", "hasf_topo.hip", "hasf_serve.hip"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions anywhere (the library has no float math at all)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result", "-Wno-unused-value", "-Wno-unused-command-line-argument",
@@ -24,19 +25,35 @@ def hipcc() -> str:
     return os.path.join(rocm, "bin", "hipcc")
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(os.path.dirname(OUT), exist_ok=True)
-    tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp] + \
-        [os.path.join(CSRC, s) for s in SOURCES]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in res.stdout.splitlines() if "packed-fp32-ops" not in l)
     if res.returncode != 0:
         sys.stderr.write(out + "\n")
-        raise RuntimeError("hipcc failed (%d)" % res.returncode)
+        raise RuntimeError("hipcc failed (%d): %s" % (res.returncode, " ".join(cmd[-3:])))
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compiles every source to an object (in parallel), then links the
+    shared library. Always compiles."""
+    os.makedirs(os.path.dirname(OUT), exist_ok=True)
+    objdir = os.path.join(os.path.dirname(OUT), "obj%d" % os.getpid())
+    os.makedirs(objdir, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    objs = [os.path.join(objdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    cmds = [[hipcc()] + HIPCC_FLAGS + inc + ["-c", "-o", o, os.path.join(CSRC, s)] for s, o in zip(SOURCES, objs)]
+    jobs = jobs or min(len(cmds), max(1, min(16, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
+    tmp = OUT + ".tmp%d" % os.getpid()
+    _run([hipcc()] + HIPCC_FLAGS + ["-shared", "-o", tmp] + objs, verbose)
     os.replace(tmp, OUT)
+    for o in objs:
+        os.remove(o)
+    os.rmdir(objdir)
     return OUT
 
 

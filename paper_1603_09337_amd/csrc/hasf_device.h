@@ -256,19 +256,32 @@ __device__ void clear_candidates(const Img<LDS>& g, int t0, int tn)
 // a phase. chg holds the serial of the last pass that changed a pixel;
 // prod[s] the serial of the last activation or pass that flagged a word of
 // sub-image s; cnt[2] are the shared live-list lengths of alternate passes
-// that use one. A pass
-// of sub-image s runs only if prod[s] grew since it last ran; a round changed
-// the set iff chg exceeds the serial at the start of the round. These words
-// are only written between the barriers that separate them from their
-// readers (prod[s] never by the pass of s), so every thread takes the same
-// decisions without extra synchronisation.
-enum { CTL_CHG = 0, CTL_CNT = 2, CTL_PROD = 4, CTL_WORDS = 8 };
+// that use one. A pass of sub-image s runs only if prod[s] grew since it last
+// ran; a round changed the set iff chg exceeds the serial at the start of
+// the round.
+//
+// prod is kept twice, by the parity of the executed passes. Between the
+// barriers that end two executed passes, every wave takes its skip decisions
+// (reading one copy) and then runs the next pass, whose changes write the
+// other copy. Without the second copy a wave that runs ahead could store
+// prod[s] of a later pass while a slower wave has still to decide whether
+// to skip pass s (waves of a per-wave pass meet no barrier before their
+// stores): it would see the new serial, run a pass the other waves skipped,
+// and the workgroup's barriers would go out of step. Each executed pass also
+// carries the read copy into the written one (atomic max: values are serials,
+// so max is the history), so the next decisions see every earlier store.
+// Activations write both copies (no decision is pending while they run).
+// chg needs no second copy: it only grows, and a wave can only store it in
+// a new round after reading, like every other wave, that the last round
+// changed something.
+enum { CTL_CHG = 0, CTL_CNT = 2, CTL_PROD = 4, CTL_WORDS = 8, CTL_PROD2 = 8, CTL_LDS_WORDS = 12 };
 
 // per-phase scheduling state (uniform registers)
 struct Sched {
     int serial;       // last serial handed out
     int npass;        // passes with a shared list (selects its length word); grid path: chunks listed
     int consumed[4];  // prod value seen when the sub-image's pass last ran
+    int rd;           // workgroup path: offset of the prod copy the next decisions read (0 or 4)
 };
 
 // start of a phase; needs a barrier before the first activation
@@ -279,7 +292,8 @@ __device__ __forceinline__ void sched_reset(const Img<LDS>& g, Sched& sc)
     sc.npass = 0;
     for (int k = 0; k < 4; ++k)
         sc.consumed[k] = 0;
-    if (threadIdx.x < CTL_WORDS)
+    sc.rd = 0;
+    if (threadIdx.x < CTL_LDS_WORDS)
         g.ctl[threadIdx.x] = 0;
 }
 
@@ -294,12 +308,14 @@ __device__ __forceinline__ void activate_row_word(const Img<LDS>& g, int row, in
         __hip_atomic_fetch_or(g.M + q, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         g.D[q] = 1;
         g.ctl[CTL_PROD + (row & 1) * 2] = serial;
+        g.ctl[CTL_PROD2 + (row & 1) * 2] = serial;
     }
     if (od) {
         const int q = g.sub(row & 1, 1) + o;
         __hip_atomic_fetch_or(g.M + q, od, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         g.D[q] = 1;
         g.ctl[CTL_PROD + (row & 1) * 2 + 1] = serial;
+        g.ctl[CTL_PROD2 + (row & 1) * 2 + 1] = serial;
     }
 }
 
@@ -312,6 +328,7 @@ __device__ __forceinline__ void activate_pixel(const Img<LDS>& g, int i, int j, 
     __hip_atomic_fetch_or(g.M + q, 1u << (c & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     g.D[q] = 1;
     g.ctl[CTL_PROD + (i & 1) * 2 + (j & 1)] = serial;
+    g.ctl[CTL_PROD2 + (i & 1) * 2 + (j & 1)] = serial;
 }
 
 // Orders the stores a wave made before it against the loads its lanes make
@@ -526,16 +543,21 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
     const uint32_t flip = thin ? 0u : ~0u;  // live = M & (S ^ flip)
     lds_i32* chg = g.ctl + CTL_CHG;
     lds_i32* lcnt = g.ctl + CTL_CNT;
-    lds_i32* prod = g.ctl + CTL_PROD;
     for (;;) {
         const int round_start = sc.serial;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int p = prod[s];
+            // decisions read one copy of prod, the pass writes the other
+            const lds_i32* prod_rd = g.ctl + CTL_PROD + sc.rd;
+            lds_i32* prod = g.ctl + CTL_PROD + (sc.rd ^ 4);
+            const int p = prod_rd[s];
             if (p <= sc.consumed[s])
                 continue;  // nothing flagged in this sub-image: the pass would change nothing
             sc.consumed[s] = p;
             const int ser = ++sc.serial;
+            if (threadIdx.x < 4)
+                __hip_atomic_fetch_max(prod + threadIdx.x, prod_rd[threadIdx.x], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             const int si = s >> 1, sj = s & 1;
             const int so = 1 - si, co = 1 - sj;
             const auto Ss = g.S + g.sub(si, sj);
@@ -674,6 +696,7 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
                 }
             }
             __syncthreads();
+            sc.rd ^= 4;
         }
         // a round changed nothing (and the level is done) iff no pass of it
         // stored its serial in chg; a round without any pass changes nothing

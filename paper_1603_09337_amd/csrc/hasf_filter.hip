@@ -647,7 +647,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void ha
 {
     extern __shared__ uint64_t smem[];
     __shared__ unsigned cnt[HASF_LEVELS_MAX];
-    __shared__ int ctl[CTL_WORDS];
+    __shared__ int ctl[CTL_LDS_WORDS];
     __shared__ int s_img;
     for (;;) {
         if (threadIdx.x == 0)

@@ -63,7 +63,7 @@ template <bool LDS>
 __device__ void topo_run(const TopoArgs& a, uint64_t* smem)
 {
     __shared__ unsigned tmp[TOPO_BLOCK / 64 + 1];
-    __shared__ int ctl[CTL_WORDS];
+    __shared__ int ctl[CTL_LDS_WORDS];
     Img<LDS> g;
     g.ctl = (lds_i32*)ctl;
     g.H = a.H;
