@@ -121,6 +121,25 @@ hasf_status hasf_edt_sq(hasf_ctx* ctx, const uint8_t* feat, int H, int W, int64_
                         int border_is_feature, uint32_t* d2, int64_t ld_out);
 
 /*
+ * hasf_edt_sq for callers that cannot allocate memory (code being captured
+ * into a HIP graph, tight serving loops, harnesses that forbid hipMalloc):
+ * the same transform, the same kernels and the same arguments and results,
+ * but it calls no hipMalloc, hipFree or other allocating routine. Its
+ * scratch (per 32-row segment and column: a feature mask and the nearest
+ * feature rows above and below, ceil(H / 32) * W * 12 + 768 bytes) lives in
+ * a device array of HASF_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each device it runs on until the process ends; 4096 x 4096 needs 6 MiB.
+ * HASF_EINVAL (nothing enqueued) for the arguments hasf_edt_sq rejects and
+ * for sizes whose scratch exceeds that maximum. Every call on one device
+ * shares the array, whichever context makes it: calls that may overlap on
+ * one GPU (other streams, other contexts, other threads) race and give
+ * undefined results; calls queued in order on one stream do not.
+ */
+#define HASF_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+hasf_status hasf_edt_sq_noalloc(hasf_ctx* ctx, const uint8_t* feat, int H, int W, int64_t ld,
+                                int border_is_feature, uint32_t* d2, int64_t ld_out);
+
+/*
  * Constrained homotopic thinning H(X, K) (Sec. 2): repeatedly deletes simple
  * points of X that are not in K, in increasing order of their squared
  * Euclidean distance to the background (outside of the window included),

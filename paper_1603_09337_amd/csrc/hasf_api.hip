@@ -19,6 +19,8 @@ hipError_t launch_topo(const TopoArgs& a, size_t lds_bytes, hipStream_t stream);
 int filter_occupancy(size_t lds_bytes, int block);
 hipError_t launch_grid(const ImgDesc* d_desc, GridCtl* d_ctl, unsigned* d_err, int grid, hipStream_t stream);
 int grid_occupancy();
+hipError_t noalloc_init(int device);
+void* noalloc_scratch(int device);
 }  // namespace hasf_detail
 
 using namespace hasf_detail;
@@ -210,6 +212,10 @@ hasf_status hasf_create(const hasf_opts* opts, hasf_ctx** out)
     e = hipGetDeviceProperties(&prop, o.device);
     if (e != hipSuccess)
         return dev_fail(nullptr, e, "hipGetDeviceProperties");
+    // the allocation-free entry points' scratch: this device's address of its copy
+    e = noalloc_init(o.device);
+    if (e != hipSuccess)
+        return dev_fail(nullptr, e, "hasf_create: address of the allocation-free scratch");
     hasf_ctx* c = new (std::nothrow) hasf_ctx();
     if (!c) {
         set_err(nullptr, "hasf_create: out of host memory");
@@ -362,6 +368,37 @@ hasf_status hasf_edt_sq(hasf_ctx* ctx, const uint8_t* feat, int H, int W, int64_
                               ctx->num_xcd, ctx->stream);
     if (e != hipSuccess)
         return dev_fail(ctx, e, "hasf_edt_sq launch");
+    return HASF_OK;
+}
+
+hasf_status hasf_edt_sq_noalloc(hasf_ctx* ctx, const uint8_t* feat, int H, int W, int64_t ld,
+                                int border_is_feature, uint32_t* d2, int64_t ld_out)
+{
+    hasf_status s = check_image(ctx, feat, H, W, ld, "hasf_edt_sq_noalloc");
+    if (s)
+        return s;
+    if (!d2 || ld_out < W) {
+        set_err(ctx, "hasf_edt_sq_noalloc: need d2 != NULL and ld_out >= W");
+        return HASF_EINVAL;
+    }
+    const size_t need = edt_scratch_bytes(H, W);
+    if (need > HASF_NOALLOC_SCRATCH_BYTES) {
+        set_err(ctx, "hasf_edt_sq_noalloc: %d x %d needs %zu bytes of scratch, more than the %zu of "
+                "HASF_NOALLOC_SCRATCH_BYTES (use hasf_edt_sq)", H, W, need, (size_t)HASF_NOALLOC_SCRATCH_BYTES);
+        return HASF_EINVAL;
+    }
+    void* scratch = noalloc_scratch(ctx->device);
+    if (!scratch) {
+        set_err(ctx, "hasf_edt_sq_noalloc: no scratch address for device %d", ctx->device);
+        return HASF_EINTERNAL;
+    }
+    hipSetDevice(ctx->device);
+    const size_t lds_max = std::min(ctx->lds_per_block, (size_t)160 * 1024);
+    // every kernel writes the scratch it reads before reading it: nothing to clear
+    hipError_t e = launch_edt(feat, H, W, ld, border_is_feature ? 1 : 0, 0, d2, ld_out, scratch, lds_max,
+                              ctx->num_xcd, ctx->stream);
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "hasf_edt_sq_noalloc launch");
     return HASF_OK;
 }
 

@@ -30,6 +30,7 @@
 // frame) every column is empty, which the strip kernel sees by itself.
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 
 #include "hasf_common.h"
 
@@ -458,6 +459,51 @@ hipError_t launch_edt(const uint8_t* F, int H, int W, long long ld, int frame, i
     hipLaunchKernelGGL(edt_rows, dim3((H + strip - 1) / strip), dim3(block), (size_t)strip * W * 2, stream, mask,
                        above, below, H, W, frame, strip, d2, ldo);
     return hipGetLastError();
+}
+
+}  // namespace hasf_detail
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free EDT entry point: the segment masks and
+// carries live in this file-scope array instead of the context's growable
+// scratch. Host code never passes the array's name to a kernel (on the host
+// it is a stand-in, not a device address): noalloc_init takes each device's
+// address of its own copy once, with that device current, and every launch
+// uses that address.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[HASF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEVICES];
+}  // namespace
+
+namespace hasf_detail {
+
+hipError_t noalloc_init(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_ptr[device])
+        return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e;
+    }
+    g_noalloc_ptr[device] = p;
+    return hipSuccess;
+}
+
+void* noalloc_scratch(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES)
+        return nullptr;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    return g_noalloc_ptr[device];
 }
 
 }  // namespace hasf_detail

@@ -23,6 +23,7 @@ HASF_EINTERNAL = -6
 HASF_R_MAX = 15
 HASF_SERVE_LANES_MAX = 16
 HASF_SERVE_PERSISTENT = 1
+HASF_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libhasf.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
@@ -84,6 +85,7 @@ _lib.hasf_last_error.restype = ctypes.c_char_p
 _lib.hasf_simple_lut.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_uint32)]
 _lib.hasf_edt_sq.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int, _vp,
                              ctypes.c_int64]
+_lib.hasf_edt_sq_noalloc.argtypes = _lib.hasf_edt_sq.argtypes
 _lib.hasf_homotopic_thin.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64]
 _lib.hasf_homotopic_thicken.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64]
 _lib.hasf_homotopic_thin_conn.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int]
@@ -96,7 +98,7 @@ _lib.hasf_filter_batch.argtypes = [_vp, ctypes.POINTER(_Image), ctypes.c_int]
 _lib.hasf_filter_labels.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_uint8), ctypes.c_int, ctypes.c_int, _vp,
                                     ctypes.c_int64, ctypes.c_int64]
-for _f in ("hasf_create", "hasf_set_stream", "hasf_sync", "hasf_simple_lut", "hasf_edt_sq",
+for _f in ("hasf_create", "hasf_set_stream", "hasf_sync", "hasf_simple_lut", "hasf_edt_sq", "hasf_edt_sq_noalloc",
            "hasf_homotopic_thin", "hasf_homotopic_thicken", "hasf_homotopic_thin_conn",
            "hasf_homotopic_thicken_conn", "hasf_filter", "hasf_filter_cd",
            "hasf_filter_batch", "hasf_filter_labels"):
@@ -195,7 +197,9 @@ class Context:
     def sync(self):
         self._check(_lib.hasf_sync(self._h))
 
-    def edt_sq(self, feat, border_is_feature: bool = False, out=None):
+    def edt_sq(self, feat, border_is_feature: bool = False, out=None, noalloc: bool = False):
+        """hasf_edt_sq, or hasf_edt_sq_noalloc when noalloc is set (then give
+        `out`: allocating it here would defeat the purpose)."""
         H, W, ld = _img(feat, "feat", self.device)
         if out is None:
             out = self._torch.empty((H, W), dtype=self._torch.int32, device=feat.device)
@@ -205,8 +209,8 @@ class Context:
             raise ValueError("out must be an (H, W) int32 or uint32 tensor with unit column stride on cuda:%d"
                              % self.device)
         self._stream()
-        self._check(_lib.hasf_edt_sq(self._h, _ptr(feat), H, W, ld, int(bool(border_is_feature)), _ptr(out),
-                                     out.stride(0)))
+        fn = _lib.hasf_edt_sq_noalloc if noalloc else _lib.hasf_edt_sq
+        self._check(fn(self._h, _ptr(feat), H, W, ld, int(bool(border_is_feature)), _ptr(out), out.stride(0)))
         return out
 
     def homotopic_thin(self, X, K=None, conn: int = 8):
