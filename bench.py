@@ -21,12 +21,19 @@ Beside it, on the same GPU:
   64 distinct drawn frames of the schedule -- with the plain path timed on
   those 64 frames;
 * edt: the exact squared EDT (hasf_edt_sq) of the 4096x4096 r=10 input, as
-  HBM GB/s against the 8 TB/s peak;
+  HBM GB/s against the 8 TB/s peak, on 9 bytes per pixel (a two-pass EDT
+  that writes and reads its column distances) and on the 5 bytes per pixel
+  this layout moves (read the features once, write the squared distances);
 * large: the whole filter on that 4096x4096 r=10 image alone;
-* roofline: the batched filter kernel, bound by VALU integer lane operations
-  (instruction counts from the committed rocprofv3 counter summary);
-* cpu_baseline: the CPU oracle on a small sample of the 512x512 images
-  (single thread).
+* roofline: the thinning and thickening rounds of that filter against HBM:
+  1.375 bytes per pixel per round (object and constraint bits read, a 1-byte
+  level map read, object bits written) times the rounds of the schedule,
+  counted on the device (hasf_get_grid_counts), over the kernel's time from
+  HIP events on the stream it runs on;
+* batch_kernel: diagnostics of the batched kernel (VALU lane operations from
+  the committed rocprofv3 counter summary against the int32 VALU peak);
+* cpu_baseline: the CPU oracle on a sample of the 512x512 images, on one
+  core and as independent processes on up to 16 host cores.
 Prints one JSON line.
 
 The served streams run one launch lane per hardware queue. --hw-queues Q
@@ -56,8 +63,15 @@ HBM_PEAK = 8.0e12  # bytes/s
 # from rocprofv3 --pmc (SQ_INSTS_VALU, FETCH_SIZE, WRITE_SIZE); each wave64
 # VALU instruction is 64 lane-ops
 PROFILE_COUNTS = os.path.join(ROOT, "profiles", "filter_512x512_r5_counters.json")
-# exact EDT: 1 byte read + 4 bytes written per pixel
-EDT_BYTES_PER_PX = 5
+# exact EDT: a two-pass EDT reads the features (1 B), writes and reads the
+# column distances g (uint16, 2 + 2 B) and writes d^2 (uint32, 4 B); this
+# layout keeps g on chip, so its compulsory bytes are 1 B read + 4 B written
+EDT_BYTES_PER_PX = 9
+EDT_BYTES_PER_PX_LAYOUT = 5
+# one round of thinning or thickening (four subfield passes over the window):
+# object bits and constraint or limit bits read (1/8 + 1/8 B), a 1-byte level
+# map read, object bits written (1/8 B)
+ROUND_BYTES_PER_PX = 1.375
 # HBM bytes per hasf_edt_sq call on the 4096x4096 input, from rocprofv3 --pmc
 # (FETCH_SIZE, WRITE_SIZE of the EDT kernels of the same calls as bench_edt)
 EDT_COUNTS = os.path.join(ROOT, "profiles", "edt_4096_counters.json")
@@ -124,13 +138,16 @@ def bench_edt(ctx, reps=20):
     torch.cuda.synchronize()
     t = e0.elapsed_time(e1) / 1e3 / reps
     bytes_ = EDT_BYTES_PER_PX * Hn * Wn
+    bytes_l = EDT_BYTES_PER_PX_LAYOUT * Hn * Wn
     traffic = None
     if os.path.exists(EDT_COUNTS):
         traffic = json.load(open(EDT_COUNTS)).get("hbm_bytes_per_call")
     return {"bound": "hbm", "achieved": round(bytes_ / t / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": round(bytes_ / t / HBM_PEAK, 4), "traffic": traffic, "us_per_call": round(t * 1e6, 1),
             "workload": "hasf_edt_sq 4096x4096, border is feature (the 4096x4096 r=10 input)",
-            "bytes_per_call": bytes_}
+            "bytes_per_px": EDT_BYTES_PER_PX, "bytes_per_call": bytes_,
+            "layout": {"bytes_per_px": EDT_BYTES_PER_PX_LAYOUT, "bytes_per_call": bytes_l,
+                       "achieved": round(bytes_l / t / 1e9, 1), "frac": round(bytes_l / t / HBM_PEAK, 4)}}
 
 
 def bench_large(ctx, reps=3):
@@ -142,6 +159,8 @@ def bench_large(ctx, reps=3):
     d = src.clone()
     ctx.filter(d, None, r)
     ctx.sync()
+    ctx.grid_counts(reset=True)
+    # the filter runs on the current stream, where the events are recorded
     stream = torch.cuda.current_stream()
     ts = []
     for _ in range(reps):
@@ -152,17 +171,30 @@ def bench_large(ctx, reps=3):
         e1.record(stream)
         ctx.sync()
         ts.append(e0.elapsed_time(e1))
+    counts = ctx.grid_counts(reset=True)
     ms = min(ts)
-    out = {"workload": "hasf 4096x4096 r=10, C empty, one image (grid of workgroups)", "ms": round(ms, 2),
-           "Mpixel_per_s": round(X.size / ms / 1e3, 2), "frames_per_s": round(1e3 / ms, 3)}
-    # the thinning and thickening passes against HBM: the measured bytes of the
-    # whole filter over its time (the passes are most of it)
+    ms_avg = sum(ts) / len(ts)
+    tiled = ctx.tile_rows >= 0
+    out = {"workload": "hasf 4096x4096 r=10, C empty, one image (%s)" %
+           ("row tiles of %d rows in LDS" % (ctx.tile_rows or 32) if tiled else "grid of workgroups"),
+           "ms": round(ms, 2), "ms_avg": round(ms_avg, 2),
+           "Mpixel_per_s": round(X.size / ms / 1e3, 2), "frames_per_s": round(1e3 / ms, 3),
+           "per_filter": {k: v / counts["launches"] for k, v in counts.items() if k != "launches"}}
+    # the thinning and thickening rounds against HBM: algorithmic bytes of the
+    # schedule's rounds (counted on the device) over the kernel's mean time
+    # (which also holds the distance stages)
+    rounds = counts["rounds"] / counts["launches"]
+    alg = ROUND_BYTES_PER_PX * X.size * rounds
+    traffic = None
     if os.path.exists(LARGE_COUNTS):
-        hbm = json.load(open(LARGE_COUNTS)).get("hbm_bytes_per_filter")
-        if hbm:
-            out["hbm"] = {"bound": "hbm", "traffic": hbm, "achieved": round(hbm / (ms / 1e3) / 1e9, 1),
-                          "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                          "frac": round(hbm / (ms / 1e3) / HBM_PEAK, 4)}
+        lc = json.load(open(LARGE_COUNTS))
+        if lc.get("kernel") == ("hasf_tile_kernel" if tiled else "hasf_grid_kernel"):
+            traffic = lc.get("hbm_bytes_per_filter")
+    out["roofline"] = {"bound": "hbm", "achieved": round(alg / (ms_avg / 1e3) / 1e9, 1), "peak": HBM_PEAK / 1e9,
+                       "unit": "GB/s", "frac": round(alg / (ms_avg / 1e3) / HBM_PEAK, 4), "traffic": traffic,
+                       "kernel": "hasf_tile_kernel" if tiled else "hasf_grid_kernel",
+                       "workload": out["workload"], "rounds": rounds, "bytes_per_px_round": ROUND_BYTES_PER_PX,
+                       "px": X.size, "algorithmic_bytes": alg, "kernel_ms": round(ms_avg, 3)}
     return out
 
 
@@ -360,6 +392,64 @@ def bench_labels(ctx, reps=5):
             "Mpixel_per_s": round(n * Hn * Wn / ms / 1e3, 2)}
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_share(args):
+    """One worker of the multi-process leg: the oracle on its images."""
+    import oracle
+    Xs, Cs = args
+    t0 = time.perf_counter()
+    for X, C in zip(Xs, Cs):
+        oracle.hasf(X, C, R)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(Xs, Cs, n, distinct):
+    """The oracle (plain C, one thread per process, as it stands) on n of the
+    512x512 r=5 images on one core, then on up to 16 host cores as
+    independent processes with 3 images each (images are independent)."""
+    import multiprocessing as mp
+    import oracle
+    log("cpu oracle: %d frames on one core" % n)
+    t0 = time.perf_counter()
+    for k in range(n):
+        oracle.hasf(Xs[k % distinct], Cs[k % distinct], R)
+    t1 = time.perf_counter()
+    one = n * H * W / (t1 - t0) / 1e6
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cores = max(1, min(16, avail))
+    per = 3
+    shares = [([Xs[(c * per + j) % distinct] for j in range(per)], [Cs[(c * per + j) % distinct] for j in range(per)])
+              for c in range(cores)]
+    log("cpu oracle: %d frames on %d processes" % (cores * per, cores))
+    ctx_mp = mp.get_context("spawn")
+    with ctx_mp.Pool(cores) as pool:
+        pool.map(_oracle_share, shares[:cores])  # start-up and library load outside the timing
+        t2 = time.perf_counter()
+        pool.map(_oracle_share, shares)
+        t3 = time.perf_counter()
+    multi = cores * per * H * W / (t3 - t2) / 1e6
+    return {"value": round(multi, 3), "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
+            "frames_per_s": round(cores * per / (t3 - t2), 3),
+            "sample": "%d of the 512x512 r=5 images (C = 200 px), %d per process on %d processes; "
+                      "one core: %d images" % (cores * per, per, cores, n),
+            "one_core": {"value": round(one, 4), "unit": "Mpixel/s", "frames_per_s": round(n / (t1 - t0), 3),
+                         "cores": 1},
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "affinity": avail,
+            "paper": "32 images/s at 512x512 on 8 cores of 2x Xeon E5405 (2 GHz), radius not stated"}
+
+
 def main():
     global HW_QUEUES
     a = parse()
@@ -434,22 +524,22 @@ def main():
     lat_ms = np.array([e0.elapsed_time(e1) for e0, e1 in lat])
     plain_fps = a.plain / (tp1 - tp0)
 
-    # roofline of the dominant kernel (the persistent filter kernel)
+    # diagnostics of the batched kernel: an image's state lives in LDS and
+    # its compulsory HBM traffic is 3 B/px, so it is not held to a roofline;
+    # how busy its vector ALUs are comes from the committed instruction counts
     kern_s = float(np.mean(kern_ms)) / 1e3
-    roof = None
+    batch_diag = {"kernel": "hasf_filter_kernel<512>", "kernel_ms": round(kern_s * 1e3, 3),
+                  "compulsory_bytes": 3 * H * W * B,
+                  "compulsory_GB_per_s": round(3 * H * W * B / kern_s / 1e9, 1)}
     counts = None
     if os.path.exists(PROFILE_COUNTS):
         counts = json.load(open(PROFILE_COUNTS))
     if counts and counts.get("valu_insts_per_image"):
         ops = counts["valu_insts_per_image"] * 64.0 * B
-        ach = ops / kern_s / 1e12
-        peak = VALU_INT32_PEAK / 1e12
-        traffic = None
+        batch_diag["valu_busy"] = round(ops / kern_s / VALU_INT32_PEAK, 4)
+        batch_diag["valu_lane_ops_per_s"] = round(ops / kern_s / 1e12, 3)
         if counts.get("hbm_bytes_per_image") is not None:
-            traffic = counts["hbm_bytes_per_image"] * B
-        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": round(peak, 3), "unit": "TFLOP/s",
-                "frac": round(ach / peak, 4), "traffic": traffic,
-                "kernel": "hasf_filter_kernel<512>", "ops": "int32 VALU lane-ops"}
+            batch_diag["traffic"] = counts["hbm_bytes_per_image"] * B
 
     log("edt 4096x4096")
     edt = bench_edt(ctx)
@@ -464,16 +554,7 @@ def main():
 
     cpu = None
     if not a.no_cpu and a.cpu_sample > 0:
-        import oracle
-        n = a.cpu_sample
-        log("cpu oracle: %d frames" % n)
-        tc0 = time.perf_counter()
-        for k in range(n):
-            oracle.hasf(Xs[k % a.distinct], Cs[k % a.distinct], R)
-        tc1 = time.perf_counter()
-        cpu = {"value": round(n * H * W / (tc1 - tc0) / 1e6, 4), "unit": "Mpixel/s", "cores": 1,
-               "kind": "oracle", "frames_per_s": round(n / (tc1 - tc0), 3),
-               "sample": "%d of the 512x512 r=5 images, oracle (plain C, 1 thread)" % n}
+        cpu = cpu_baseline(Xs, Cs, a.cpu_sample, a.distinct)
 
     out = {
         "metric": "Mpixel/s and frames/s for HASF 512^2 r=5 (batched vs plain); p50/p99 frame latency",
@@ -507,7 +588,8 @@ def main():
         "edt": edt,
         "large": large,
         "labels": labels,
-        "roofline": roof,
+        "batch_kernel": batch_diag,
+        "roofline": large["roofline"],
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -74,7 +74,13 @@ typedef struct {
                                grid. 0 = HASF_GRID_MIN_PIXELS_DEFAULT; SIZE_MAX = never */
     size_t batch_grid_min_pixels; /* the same for batches of several images and served frames.
                                      0 = HASF_BATCH_GRID_MIN_PIXELS_DEFAULT; SIZE_MAX = never */
+    int tile_rows;          /* large images (hasf_filter, hasf_filter_cd, batches) whose rows fit are filtered
+                               by row tiles of this many rows, each tile's state in LDS, exchanging halo rows
+                               every two rounds; 0 = HASF_TILE_ROWS_DEFAULT; an even number >= 8; -1 = never
+                               (the grid of workgroups with the state in global memory) */
 } hasf_opts;
+
+#define HASF_TILE_ROWS_DEFAULT 32
 
 /* Create a context on opts->device (opts may be NULL: device 0, defaults).
  * The context owns its scratch memory and the default (null) stream. */
@@ -96,6 +102,25 @@ hasf_status hasf_sync(hasf_ctx* ctx);
 const char* hasf_strerror(int status);
 /* Detail of the last failure on ctx (ctx may be NULL: last failure on this thread). */
 const char* hasf_last_error(const hasf_ctx* ctx);
+
+/*
+ * Schedule counts of the images filtered by a grid of workgroups (hasf_filter,
+ * hasf_filter_cd and batches; not served frames), summed over the launches
+ * since the context was created or last reset: one launch per image; the
+ * rounds of the thinnings and thickenings (a round is the four subfield
+ * passes over the whole image; a level that activated candidates takes its
+ * rounds up to and including the first that changed nothing; this count is
+ * a property of the schedule, not of how it is run); the distance levels
+ * that activated candidates; and the grid-wide barriers. Waits for ctx's
+ * stream. reset != 0 zeroes the counts after reading them.
+ */
+typedef struct {
+    uint64_t launches;
+    uint64_t rounds;
+    uint64_t levels;
+    uint64_t barriers;
+} hasf_grid_counts;
+hasf_status hasf_get_grid_counts(hasf_ctx* ctx, hasf_grid_counts* out, int reset);
 
 /*
  * Simple-point table (Sec. 2, topological numbers T and T-bar; a point is

@@ -19,6 +19,8 @@ hipError_t launch_topo(const TopoArgs& a, size_t lds_bytes, hipStream_t stream);
 int filter_occupancy(size_t lds_bytes, int block);
 hipError_t launch_grid(const ImgDesc* d_desc, GridCtl* d_ctl, unsigned* d_err, int grid, hipStream_t stream);
 int grid_occupancy();
+hipError_t launch_tile(const ImgDesc* d_desc, TileCtl* d_ctl, unsigned* d_err, const TilePlan& P,
+                       hipStream_t stream);
 hipError_t noalloc_init(int device);
 void* noalloc_scratch(int device);
 }  // namespace hasf_detail
@@ -195,6 +197,10 @@ hasf_status hasf_create(const hasf_opts* opts, hasf_ctx** out)
         set_err(nullptr, "hasf_create: flags must be 0");
         return HASF_EINVAL;
     }
+    if (o.tile_rows < -1 || (o.tile_rows > 0 && (o.tile_rows < TILE_HALO || (o.tile_rows & 1)))) {
+        set_err(nullptr, "hasf_create: tile_rows must be -1, 0 or an even number >= %d", TILE_HALO);
+        return HASF_EINVAL;
+    }
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev == 0) {
@@ -240,6 +246,7 @@ hasf_status hasf_create(const hasf_opts* opts, hasf_ctx** out)
     c->d_counter = nullptr;
     c->grid_min_px = o.grid_min_pixels ? o.grid_min_pixels : HASF_GRID_MIN_PIXELS_DEFAULT;
     c->batch_grid_min_px = o.batch_grid_min_pixels ? o.batch_grid_min_pixels : HASF_BATCH_GRID_MIN_PIXELS_DEFAULT;
+    c->tile_rows = o.tile_rows;
     c->d_grid_err = nullptr;
     c->grid_pending = false;
     c->side = nullptr;
@@ -347,6 +354,32 @@ hasf_status hasf_sync(hasf_ctx* ctx)
             return HASF_EINTERNAL;
         }
     }
+    return HASF_OK;
+}
+
+hasf_status hasf_get_grid_counts(hasf_ctx* ctx, hasf_grid_counts* out, int reset)
+{
+    if (!ctx || !out) {
+        set_err(ctx, "hasf_get_grid_counts: need ctx and out");
+        return HASF_EINVAL;
+    }
+    hipSetDevice(ctx->device);
+    unsigned long long c[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(c, ctx->d_grid_err + GRID_COUNTS_OFF, sizeof c, hipMemcpyDeviceToHost,
+                                  ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess && reset) {
+        e = hipMemsetAsync(ctx->d_grid_err + GRID_COUNTS_OFF, 0, sizeof c, ctx->stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(ctx->stream);
+    }
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "hasf_get_grid_counts");
+    out->launches = c[0];
+    out->rounds = c[1];
+    out->levels = c[2];
+    out->barriers = c[3];
     return HASF_OK;
 }
 
@@ -465,12 +498,28 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
     // meta block copied in one transfer: [queue counter | small descriptors |
     // per big image: GridCtl, descriptor]; then the planes and level entries
     const size_t desc_bytes = align256(256 + sizeof(ImgDesc) * (size_t)ns);
-    const size_t gmeta = align256(sizeof(GridCtl)) + 256;
+    const size_t gmeta = align256(std::max(sizeof(GridCtl), sizeof(TileCtl))) + 256;
     const size_t meta_bytes = desc_bytes + gmeta * (size_t)nb;
     std::vector<ImgDesc> desc(n);
+    // a large image goes to row tiles in LDS when its rows fit a tile's band,
+    // else to the grid kernel with its state in global memory
+    std::vector<TilePlan> tiles(nb);
+    for (int q = 0; q < nb; ++q) {
+        const hasf_image& im = imgs[big[q]];
+        tiles[q].ok = false;
+        if (ctx->tile_rows >= 0)
+            tiles[q] = tile_plan(im.H, im.W, im.r, lds_cap, ctx->num_cu, ctx->tile_rows);
+    }
     size_t bytes = 0, lds_need = 0;
-    auto lay_out = [&](ImgDesc& d, const hasf_image& im, size_t cap) {
-        const ImageLayout L = image_layout(im.H, im.W, im.r, cap);
+    auto lay_out = [&](ImgDesc& d, const hasf_image& im, size_t cap, const TilePlan* tp) {
+        ImageLayout L = image_layout(im.H, im.W, im.r, cap);
+        if (tp) {
+            L.lds = false;
+            L.lds_bytes = tp->lds_bytes;
+            L.planes_bytes = tp->planes_bytes;
+            L.idx_bytes = tp->idx_bytes;
+            L.msk_bytes = tp->msk_bytes;
+        }
         d.X = im.X;
         d.C = im.C;
         d.ld = im.ld;
@@ -491,9 +540,9 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
         return L;
     };
     for (int q = 0; q < ns; ++q)
-        lds_need = std::max(lds_need, lay_out(desc[q], imgs[order[q]], lds_cap).lds_bytes);
-    for (int q = 0; q < nb; ++q)
-        lay_out(desc[ns + q], imgs[big[q]], 0);  // grid images keep their state in global memory
+        lds_need = std::max(lds_need, lay_out(desc[q], imgs[order[q]], lds_cap, nullptr).lds_bytes);
+    for (int q = 0; q < nb; ++q)  // grid images keep their state in global memory
+        lay_out(desc[ns + q], imgs[big[q]], 0, tiles[q].ok ? &tiles[q] : nullptr);
     hasf_status s = ensure_scratch(ctx, bytes + meta_bytes);
     if (s)
         return s;
@@ -510,7 +559,7 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
     std::memset(host, 0, meta_bytes);
     std::memcpy(host + 256, desc.data(), sizeof(ImgDesc) * (size_t)ns);
     for (int q = 0; q < nb; ++q)
-        std::memcpy(host + desc_bytes + gmeta * q + align256(sizeof(GridCtl)), &desc[ns + q], sizeof(ImgDesc));
+        std::memcpy(host + desc_bytes + gmeta * q + gmeta - 256, &desc[ns + q], sizeof(ImgDesc));
     // stream-ordered after the previous call's kernels, which read the same
     // device region; the staging buffer is free again once the event passes
     hipError_t e = hipMemcpyAsync(base, host, meta_bytes, hipMemcpyHostToDevice, ctx->stream);
@@ -548,12 +597,19 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
     }
     for (int q = 0; q < nb; ++q) {
         const ImgDesc& d = desc[ns + q];
-        const int nwd = d.H * ((d.W + 63) / 64);
-        const int grid = grid_blocks(nwd, ctx->num_cu * grid_occupancy() / 2);
         char* m = base + desc_bytes + gmeta * q;
-        e = launch_grid((const ImgDesc*)(m + align256(sizeof(GridCtl))), (GridCtl*)m, ctx->d_grid_err, grid, gs);
-        if (e != hipSuccess)
-            return dev_fail(ctx, e, "hasf_grid_kernel launch");
+        const ImgDesc* dd = (const ImgDesc*)(m + gmeta - 256);
+        if (tiles[q].ok) {
+            e = launch_tile(dd, (TileCtl*)m, ctx->d_grid_err, tiles[q], gs);
+            if (e != hipSuccess)
+                return dev_fail(ctx, e, "hasf_tile_kernel launch");
+        } else {
+            const int nwd = d.H * ((d.W + 63) / 64);
+            const int grid = grid_blocks(nwd, ctx->num_cu * grid_occupancy() / 2);
+            e = launch_grid(dd, (GridCtl*)m, ctx->d_grid_err, grid, gs);
+            if (e != hipSuccess)
+                return dev_fail(ctx, e, "hasf_grid_kernel launch");
+        }
         ctx->grid_pending = true;
     }
     if (gs != ctx->stream) {

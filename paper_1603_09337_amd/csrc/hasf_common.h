@@ -140,6 +140,12 @@ struct ImgDesc {
 // zeroed before each launch): the grid barrier (arrival count, generation,
 // abort flag), an error word, the pass control words by barrier-epoch parity
 // and the level entry counts.
+// The context's grid word block (256 bytes): word 0 is the sticky error
+// word; from word GRID_COUNTS_OFF on, four uint64 counts summed over grid
+// launches: launches, rounds of the level loops, levels activated, grid
+// barriers.
+constexpr int GRID_COUNTS_OFF = 16;
+
 struct GridCtl {
     unsigned bar_count, pad0[63];
     unsigned bar_gen, pad1[63];
@@ -147,6 +153,44 @@ struct GridCtl {
     int ctl[2][8];
     unsigned cnt[HASF_LEVELS_MAX];
 };
+
+// Control block of one image filtered by row tiles (device memory, zeroed
+// before each launch): the grid barrier, an error word, the last round that
+// changed one of a tile's own rows (1-based over the launch, kept twice by
+// barrier parity), and per phase (4 per radius) and level whether some tile
+// has candidates.
+struct TileCtl {
+    unsigned bar_count, pad0[63];
+    unsigned bar_gen, pad1[63];
+    unsigned abort, err, pad2[62];
+    unsigned last_change[2], pad3[62];
+    unsigned lev[4 * HASF_R_MAX][HASF_LEVELS_MAX];
+};
+
+// Row tiles: halo rows kept on each side of a tile, and rounds a tile runs
+// between two exchanges (a pass moves information by one row, a round is
+// four passes).
+constexpr int TILE_HALO = 8;
+constexpr int TILE_EPOCH_ROUNDS = TILE_HALO / 4;
+constexpr int TILE_NT = 1024;  // threads of a tile's workgroup
+
+// Tiling of one image: tiles of TH own rows (TH even, >= TILE_HALO), the
+// last one shorter; each keeps up to ER = TH + 2 TILE_HALO rows in LDS.
+struct TilePlan {
+    bool ok;
+    int TH, ntiles, ER;
+    size_t lds_bytes;     // dynamic LDS of a tile
+    size_t planes_bytes;  // Rg, A, K, Dp (row-major), two exchange copies (sub-images)
+    size_t ent_words;     // level entry slots per tile: levels(r) x ER x WW
+    size_t idx_bytes, msk_bytes;
+    size_t total() const { return planes_bytes + idx_bytes + msk_bytes; }
+};
+
+__host__ __device__ inline size_t tile_sub_words(int H, int W)  // one exchange copy: 4 sub-images of 32-bit words
+{
+    const size_t WW = (size_t)(W + 63) / 64, HH = (size_t)(H + 1) / 2;
+    return 4 * ((HH * WW + 3) & ~(size_t)3);
+}
 
 // Scratch of one image in the filter kernel: global bytes for the state (when
 // it does not fit in LDS), the saved set A and the constraint K, and the level
@@ -159,7 +203,7 @@ struct ImageLayout {
     size_t total() const { return planes_bytes + idx_bytes + msk_bytes; }
 };
 
-inline size_t hasf_align256(size_t x) { return (x + 255) / 256 * 256; }
+__host__ __device__ inline size_t hasf_align256(size_t x) { return (x + 255) / 256 * 256; }
 
 // Raises a kernel's dynamic LDS limit to `bytes` on the current device, once
 // per device (bit d of `done` records device d; devices past 63 set it on
@@ -196,6 +240,50 @@ inline ImageLayout image_layout(int H, int W, int r, size_t lds_cap)
     L.idx_bytes = hasf_align256(nlev * NWD * 4);
     L.msk_bytes = hasf_align256(nlev * NWD * 8);
     return L;
+}
+
+// Own rows per tile when the caller does not choose.
+constexpr int TILE_ROWS_DEFAULT = HASF_TILE_ROWS_DEFAULT;
+
+// Tiling of an H x W image at radius r with tiles of TH_req own rows (0: the
+// default), at most max_tiles tiles (taller tiles when needed). Not ok when a
+// band of TILE_HALO own rows and its halos does not fit lds_cap bytes of LDS
+// (very wide images), or when the image would be one tile.
+inline TilePlan tile_plan(int H, int W, int r, size_t lds_cap, int max_tiles, int TH_req)
+{
+    TilePlan P{};
+    P.ok = false;
+    const size_t WW = (size_t)(W + 63) / 64, NWD = (size_t)H * WW;
+    int ercap = 0;
+    while (ercap < H + 2 * TILE_HALO && hasf_align256(state_bytes(ercap + 2, W, true)) <= lds_cap)
+        ercap += 2;
+    const int thmax = ((ercap - 2 * TILE_HALO) / 2) * 2;
+    if (thmax < TILE_HALO || max_tiles < 2)
+        return P;
+    int th = TH_req > 0 ? TH_req : TILE_ROWS_DEFAULT;
+    th = th < TILE_HALO ? TILE_HALO : th;
+    th = (th + 1) / 2 * 2;
+    th = th > thmax ? thmax : th;
+    if ((H + th - 1) / th > max_tiles) {
+        th = (H + max_tiles - 1) / max_tiles;
+        th = (th + 1) / 2 * 2;
+        if (th > thmax)
+            return P;
+    }
+    const int nt = (H + th - 1) / th;
+    if (nt < 2)
+        return P;
+    P.ok = true;
+    P.TH = th;
+    P.ntiles = nt;
+    P.ER = th + 2 * TILE_HALO < H ? th + 2 * TILE_HALO : H;
+    P.lds_bytes = hasf_align256(state_bytes(P.ER, W, true));
+    P.planes_bytes = hasf_align256(4 * NWD * 8) + 2 * hasf_align256(tile_sub_words(H, W) * 4);
+    const size_t nlev = (size_t)(r > 0 ? hasf_levels(r) : 1);
+    P.ent_words = nlev * (size_t)P.ER * WW;
+    P.idx_bytes = hasf_align256((size_t)nt * P.ent_words * 4);
+    P.msk_bytes = hasf_align256((size_t)nt * P.ent_words * 8);
+    return P;
 }
 
 // Arguments of the standalone thinning / thickening kernel.
@@ -238,6 +326,9 @@ struct hasf_ctx {
     // images of at least this many pixels are filtered by a grid of
     // workgroups: alone (hasf_filter, a batch of one), in batches and served
     size_t grid_min_px, batch_grid_min_px;
+    // own rows per tile of the row-tile path for large images (0: default;
+    // -1: large images always go to the grid kernel)
+    int tile_rows;
     // sticky device word set by a grid launch whose barrier gave up; read and
     // cleared by hasf_sync when grid work was enqueued since the last check
     unsigned* d_grid_err;

@@ -274,7 +274,10 @@ __device__ void clear_candidates(const Img<LDS>& g, int t0, int tn)
 // chg needs no second copy: it only grows, and a wave can only store it in
 // a new round after reading, like every other wave, that the last round
 // changed something.
-enum { CTL_CHG = 0, CTL_CNT = 2, CTL_PROD = 4, CTL_WORDS = 8, CTL_PROD2 = 8, CTL_LDS_WORDS = 12 };
+// TILE rounds (see run_rounds) flag a change of the tile's own rows in round
+// k at CTL_TCHG + k.
+enum { CTL_CHG = 0, CTL_CNT = 2, CTL_PROD = 4, CTL_WORDS = 8, CTL_PROD2 = 8, CTL_TCHG = 12, CTL_LDS_WORDS = 16 };
+constexpr int TILE_ROUNDS_MAX = 4;
 
 // per-phase scheduling state (uniform registers)
 struct Sched {
@@ -518,8 +521,16 @@ __device__ __forceinline__ bool test_word(const PassPtrs<LDS>& p, int idx, int r
 // per wave, and each wave lists and tests its own chunk's words, which saves
 // the workgroup barrier between listing and testing.
 // NT: the workgroup size (threads) the caller is launched with.
-template <bool LDS, int NT = BLOCK>
-__device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& sc)
+//
+// TILE: the state is one tile of a larger image (its own rows plus halo rows
+// whose values a neighbouring tile owns). Exactly `nrounds` (at most
+// TILE_ROUNDS_MAX) rounds run, since the caller decides when the level ends
+// over all tiles, and the result is the number k of rounds run until the
+// last one that changed one of the tile's own rows [ilo, ihi) (0: none did).
+// Otherwise the result is 0.
+template <bool LDS, int NT = BLOCK, bool TILE = false>
+__device__ __forceinline__ int run_rounds(const Img<LDS>& g, bool thin, Sched& sc, int nrounds = 0, int ilo = 0,
+                                          int ihi = 0)
 {
     const int WW = g.WW;
     const float invWW = 1.0f / (float)WW;
@@ -543,7 +554,14 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
     const uint32_t flip = thin ? 0u : ~0u;  // live = M & (S ^ flip)
     lds_i32* chg = g.ctl + CTL_CHG;
     lds_i32* lcnt = g.ctl + CTL_CNT;
-    for (;;) {
+    if constexpr (TILE) {
+        if (threadIdx.x < TILE_ROUNDS_MAX)
+            g.ctl[CTL_TCHG + threadIdx.x] = 0;
+        __syncthreads();
+    }
+    for (int rnd = 0;; ++rnd) {
+        if (TILE && rnd == nrounds)
+            break;
         const int round_start = sc.serial;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -567,6 +585,14 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
             const int nw = rows * WW;
             const PassPtrs<LDS> pp = pass_ptrs(g, si, sj);
             bool changed_here = false;
+            bool changed_own = false;  // TILE: a change in rows [ilo, ihi)
+            auto test = [&](int idx) {
+                const int rr = row_of(idx);
+                const bool c = test_word(pp, idx, rr, si, sj, WW, g.H, flip, g.conn4);
+                changed_here |= c;
+                if constexpr (TILE)
+                    changed_own |= c && 2 * rr + si >= ilo && 2 * rr + si < ihi;
+            };
             if (nw <= 2 * NT) {
                 // one chunk of 128 words per wave, listed at L[w0 ..] and
                 // tested by the same wave: a test writes only its own word of
@@ -610,10 +636,8 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
                     if (nl > 0) Lw[off] = q0;
                     if (nl > 1) Lw[off + 1] = q1;
                     wave_sync();
-                    for (int t = lane; t < (int)tot; t += 64) {
-                        const int idx = (int)Lw[t];
-                        changed_here |= test_word(pp, idx, row_of(idx), si, sj, WW, g.H, flip, g.conn4);
-                    }
+                    for (int t = lane; t < (int)tot; t += 64)
+                        test((int)Lw[t]);
                 }
             } else {
                 lds_i32* cnt = lcnt + (sc.npass & 1);
@@ -676,10 +700,8 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
                     lcnt[(sc.npass + 1) & 1] = 0;  // every thread read it one pass ago
                 const int n = *cnt;
                 // test the listed words
-                for (int t = threadIdx.x; t < n; t += NT) {
-                    const int idx = (int)g.L[t];
-                    changed_here |= test_word(pp, idx, row_of(idx), si, sj, WW, g.H, flip, g.conn4);
-                }
+                for (int t = threadIdx.x; t < n; t += NT)
+                    test((int)g.L[t]);
                 ++sc.npass;
             }
             // one lane per wave records the change (a same-address store from
@@ -687,12 +709,18 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
             {
                 const uint64_t chm = __ballot(changed_here);
                 if (chm && (int)(threadIdx.x & 63) == __ffsll((long long)chm) - 1) {
-                    *chg = ser;
+                    if (!TILE)
+                        *chg = ser;
                     prod[si * 2 + co] = ser;
                     if (g.H > 1) {
                         prod[so * 2 + sj] = ser;
                         prod[so * 2 + co] = ser;
                     }
+                }
+                if constexpr (TILE) {
+                    const uint64_t com = __ballot(changed_own);
+                    if (com && (int)(threadIdx.x & 63) == __ffsll((long long)com) - 1)
+                        g.ctl[CTL_TCHG + rnd] = 1;
                 }
             }
             __syncthreads();
@@ -700,7 +728,7 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
         }
         // a round changed nothing (and the level is done) iff no pass of it
         // stored its serial in chg; a round without any pass changes nothing
-        if (*chg <= round_start)
+        if (!TILE && *chg <= round_start)
             break;
     }
     // The skip decisions after the last executed pass read prod and chg with
@@ -709,6 +737,13 @@ __device__ __forceinline__ void run_rounds(const Img<LDS>& g, bool thin, Sched& 
     // run a pass the others skipped and leave the workgroup's barriers out
     // of step. Every wave finishes its decisions before anyone goes on.
     __syncthreads();
+    int last = 0;
+    if constexpr (TILE) {
+        for (int k = 0; k < nrounds; ++k)
+            if (g.ctl[CTL_TCHG + k])
+                last = k + 1;
+    }
+    return last;
 }
 
 }  // namespace hasf_dev

@@ -305,7 +305,9 @@ __device__ __attribute__((noinline)) void run_image(const ImgDesc* __restrict__ 
 struct GridSync {
     GridCtl* gc;
     unsigned nblk;
-    unsigned gen;  // grid barriers completed: the current epoch, uniform over the grid
+    unsigned gen;     // grid barriers completed: the current epoch, uniform over the grid
+    unsigned rounds;  // rounds of the level loops (uniform)
+    unsigned acts;    // levels activated (uniform)
 };
 
 // a grid barrier that waits longer than this (100 MHz ticks: 4 s) gives up
@@ -413,6 +415,7 @@ __device__ __forceinline__ bool rounds_grid(const Img<false>& g, GridSync& gs, i
     const uint32_t flip = thin ? 0u : ~0u;
     CtlView v = ctl_view(gs);
     for (;;) {
+        ++gs.rounds;
         const int round_start = sc.serial;
         for (int s = 0; s < 4; ++s) {
             const int p = v.w[CTL_PROD + s];
@@ -530,6 +533,7 @@ __device__ __forceinline__ bool level_loop_grid(const Img<false>& g, GridSync& g
         if (c == 0)
             continue;
         const int ser = ++sc.serial;
+        ++gs.acts;
         const size_t e0 = (size_t)k * g.NWD;
         unsigned touched = 0;  // bit s: a word of sub-image s was activated
         for (unsigned t = t0; t < c; t += tn) {
@@ -567,9 +571,8 @@ __device__ __forceinline__ bool level_loop_grid(const Img<false>& g, GridSync& g
 
 // The whole filter on one image, over the grid (as run_image).
 __device__ __forceinline__ bool run_image_grid(const ImgDesc* __restrict__ dp, GridCtl* gc, int* s_ok,
-                                               lds_u32* list, lds_u32* lcount)
+                                               lds_u32* list, lds_u32* lcount, GridSync& gs)
 {
-    GridSync gs{gc, gridDim.x, 0u};
     const int t0 = blockIdx.x * BLOCK + threadIdx.x, tn = gridDim.x * BLOCK;
     const Img<false> g = make_img<false>(dp, nullptr, nullptr);
     pack_rows(dp->X, dp->C, dp->ld, g.H, g.W, g.R, g.hasK ? g.K : nullptr, t0, tn);
@@ -631,10 +634,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     __shared__ int s_ok;
     __shared__ uint32_t list[GRID_LIST];
     __shared__ uint32_t lcount[2];
-    if (!run_image_grid(dp, gc, &s_ok, (lds_u32*)list, (lds_u32*)lcount) && threadIdx.x == 0) {
+    GridSync gs{gc, gridDim.x, 0u, 0u, 0u};
+    const bool ok = run_image_grid(dp, gc, &s_ok, (lds_u32*)list, (lds_u32*)lcount, gs);
+    if (!ok && threadIdx.x == 0) {
         __hip_atomic_store(&gc->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (err_out)
             __hip_atomic_fetch_or(err_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // the schedule's counts (uniform over the grid: workgroup 0 reports them)
+    if (ok && err_out && blockIdx.x == 0 && threadIdx.x == 0) {
+        unsigned long long* c = reinterpret_cast<unsigned long long*>(err_out + GRID_COUNTS_OFF);
+        __hip_atomic_fetch_add(c + 0, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(c + 1, (unsigned long long)gs.rounds, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(c + 2, (unsigned long long)gs.acts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(c + 3, (unsigned long long)gs.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

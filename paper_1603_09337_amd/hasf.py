@@ -37,7 +37,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 class _Opts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("hbm_budget", ctypes.c_size_t), ("flags", ctypes.c_uint),
-                ("grid_min_pixels", ctypes.c_size_t), ("batch_grid_min_pixels", ctypes.c_size_t)]
+                ("grid_min_pixels", ctypes.c_size_t), ("batch_grid_min_pixels", ctypes.c_size_t),
+                ("tile_rows", ctypes.c_int)]
 
 
 class _Image(ctypes.Structure):
@@ -105,6 +106,15 @@ for _f in ("hasf_create", "hasf_set_stream", "hasf_sync", "hasf_simple_lut", "ha
     getattr(_lib, _f).restype = ctypes.c_int
 
 
+class _GridCounts(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("rounds", ctypes.c_uint64), ("levels", ctypes.c_uint64),
+                ("barriers", ctypes.c_uint64)]
+
+
+_lib.hasf_get_grid_counts.argtypes = [_vp, ctypes.POINTER(_GridCounts), ctypes.c_int]
+_lib.hasf_get_grid_counts.restype = ctypes.c_int
+
+
 class HasfError(RuntimeError):
     def __init__(self, status: int, detail: str):
         super().__init__("%s (%d): %s" % (_lib.hasf_strerror(status).decode(), status, detail))
@@ -164,12 +174,13 @@ def _companion(T, X, name):
 
 class Context:
     def __init__(self, device: int = 0, hbm_budget: int = 0, grid_min_pixels: int = 0,
-                 batch_grid_min_pixels: int = 0):
+                 batch_grid_min_pixels: int = 0, tile_rows: int = 0):
         import torch
         self._torch = torch
         self.device = device
+        self.tile_rows = tile_rows
         h = _vp()
-        opts = _Opts(device, hbm_budget, 0, grid_min_pixels, batch_grid_min_pixels)
+        opts = _Opts(device, hbm_budget, 0, grid_min_pixels, batch_grid_min_pixels, tile_rows)
         st = _lib.hasf_create(ctypes.byref(opts), ctypes.byref(h))
         if st != HASF_OK:
             raise HasfError(st, _lib.hasf_last_error(None).decode())
@@ -196,6 +207,13 @@ class Context:
 
     def sync(self):
         self._check(_lib.hasf_sync(self._h))
+
+    def grid_counts(self, reset: bool = False):
+        """hasf_get_grid_counts: launches, rounds, levels, barriers of the
+        grid-filtered images since creation or the last reset."""
+        c = _GridCounts()
+        self._check(_lib.hasf_get_grid_counts(self._h, ctypes.byref(c), int(bool(reset))))
+        return {k: int(getattr(c, k)) for k, _ in _GridCounts._fields_}
 
     def edt_sq(self, feat, border_is_feature: bool = False, out=None, noalloc: bool = False):
         """hasf_edt_sq, or hasf_edt_sq_noalloc when noalloc is set (then give

@@ -1,7 +1,7 @@
 """Parity of HASF^{C,D} and the (4,8) connectivity pair (hasf_filter_cd and
 the D / conn fields of hasf_image) with the oracle, bit-exact, on every path:
-one workgroup (state in LDS and in global memory), the grid, batches and the
-served stream."""
+one workgroup (state in LDS and in global memory), the grid, row tiles,
+batches and the served stream."""
 import numpy as np
 import pytest
 import torch
@@ -18,7 +18,8 @@ _CTX = {}
 def _c(kind):
     if kind not in _CTX:
         big = 2**64 - 1
-        _CTX[kind] = {"grid": lambda: hasf.Context(0, grid_min_pixels=1, batch_grid_min_pixels=1),
+        _CTX[kind] = {"grid": lambda: hasf.Context(0, grid_min_pixels=1, batch_grid_min_pixels=1, tile_rows=-1),
+                      "tile": lambda: hasf.Context(0, grid_min_pixels=1, batch_grid_min_pixels=1, tile_rows=8),
                       "wg": lambda: hasf.Context(0, grid_min_pixels=big, batch_grid_min_pixels=big)}[kind]()
     return _CTX[kind]
 
@@ -47,13 +48,13 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("path", ["default", "grid"])
+@pytest.mark.parametrize("path", ["default", "grid", "tile"])
 def test_cd_random(case, path):
     H, W, dens, r, wc, wd, n = case
     X = synth.random_binary(H, W, dens, 1000 + H + W + r)
     C = synth.random_binary(H, W, 0.03, 1100 + H) if wc else None
     D = _background(X, 0.3, 1200 + W) if wd else None
-    c = ctx() if path == "default" else _c("grid")
+    c = ctx() if path == "default" else _c(path)
     say("cd", case, path)
     assert np.array_equal(_run(c, X, C, D, r, n), oracle.hasf(X, C, r, D=D, n=n))
 
@@ -70,6 +71,7 @@ def test_cd_shapes_workload_and_global_state():
     expg = oracle.hasf(Xg, None, 3, D=Dg, n=4)
     assert np.array_equal(_run(_c("wg"), Xg, None, Dg, 3, 4), expg)
     assert np.array_equal(_run(_c("grid"), Xg, None, Dg, 3, 4), expg)
+    assert np.array_equal(_run(_c("tile"), Xg, None, Dg, 3, 4), expg)
 
 
 def test_cd_batch_and_stream_mix_pairs_and_constraints():

@@ -18,7 +18,7 @@ _CTX = {}
 
 def grid_ctx():
     if "grid" not in _CTX:
-        _CTX["grid"] = hasf.Context(0, grid_min_pixels=1, batch_grid_min_pixels=1)
+        _CTX["grid"] = hasf.Context(0, grid_min_pixels=1, batch_grid_min_pixels=1, tile_rows=-1)
     return _CTX["grid"]
 
 

@@ -13,22 +13,23 @@ pytestmark = pytest.mark.gpu
 _GRID = {}
 
 
-def grid_ctx():
-    if "c" not in _GRID:
-        _GRID["c"] = hasf.Context(0, grid_min_pixels=1, batch_grid_min_pixels=1)
-    return _GRID["c"]
+def grid_ctx(kind="grid"):
+    if kind not in _GRID:
+        _GRID[kind] = hasf.Context(0, grid_min_pixels=1, batch_grid_min_pixels=1,
+                                   tile_rows=-1 if kind == "grid" else 8)
+    return _GRID[kind]
 
 
 def _img(H, W, seed):
     return synth.disks_image(H, W, np.random.default_rng(seed))
 
 
-@pytest.mark.parametrize("grid", [False, True])
-def test_max_radius(grid):
+@pytest.mark.parametrize("path", ["wg", "grid", "tile"])
+def test_max_radius(path):
     X = _img(120, 150, 31)
     C = synth.random_binary(120, 150, 0.02, 32)
-    c = grid_ctx() if grid else ctx()
-    say("r = HASF_R_MAX", "grid" if grid else "one workgroup")
+    c = grid_ctx(path) if path != "wg" else ctx()
+    say("r = HASF_R_MAX", path)
     d = dev(X)
     c.filter(d, dev(C), hasf.HASF_R_MAX)
     c.sync()

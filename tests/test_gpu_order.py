@@ -1,7 +1,7 @@
 """Parity of the dual filter order (hasf_image.order = 1: at every radius the
 filling first, then the cutting) with the oracle, bit-exact, on every path:
-one workgroup (state in LDS and in global memory), the grid, batches mixing
-both orders, and the served stream."""
+one workgroup (state in LDS and in global memory), the grid, row tiles,
+batches mixing both orders, and the served stream."""
 import numpy as np
 import pytest
 
@@ -14,10 +14,11 @@ pytestmark = pytest.mark.gpu
 _CTX = {}
 
 
-def _grid():
-    if "grid" not in _CTX:
-        _CTX["grid"] = hasf.Context(0, grid_min_pixels=1, batch_grid_min_pixels=1)
-    return _CTX["grid"]
+def _grid(kind="grid"):
+    if kind not in _CTX:
+        _CTX[kind] = hasf.Context(0, grid_min_pixels=1, batch_grid_min_pixels=1,
+                                  tile_rows=-1 if kind == "grid" else 8)
+    return _CTX[kind]
 
 
 def _background(X, p, seed):
@@ -43,13 +44,13 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("path", ["default", "grid"])
+@pytest.mark.parametrize("path", ["default", "grid", "tile"])
 def test_dual_order_random(case, path):
     H, W, dens, r, wc, wd, n = case
     X = synth.random_binary(H, W, dens, 2000 + H + W + r)
     C = synth.random_binary(H, W, 0.03, 2100 + H) if wc else None
     D = _background(X, 0.3, 2200 + W) if wd else None
-    c = ctx() if path == "default" else _grid()
+    c = ctx() if path == "default" else _grid(path)
     say("dual order", case, path)
     got = _run(c, X, C, D, r, n)
     assert np.array_equal(got, oracle.hasf(X, C, r, D=D, n=n, order=1))
