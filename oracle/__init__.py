@@ -70,6 +70,9 @@ def _load():
     lib.oracle_hasf_order.argtypes = [U8P, U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, U8P]
     lib.oracle_hasf.restype = ctypes.c_long
+    lib.oracle_hasf_inf.argtypes = [U8P, U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.oracle_hasf_inf.restype = ctypes.c_long
     lib.oracle_hasf_queue.argtypes = [U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.oracle_hasf_queue.restype = ctypes.c_long
     _lib = lib
@@ -205,6 +208,20 @@ def hasf(X, C, r: int, stages: bool = False, queue: bool = False, D=None, n: int
         d, dp = _opt_u8(D)
         _check(_load().oracle_hasf_cd(x.ctypes.data_as(U8P), cp, dp, H, W, r, n, sp), "hasf_cd")
     return (x, st[:r]) if stages else x
+
+
+def hasf_inf(X, C=None, D=None, n: int = 8, order: int = 0, r_max: int = 0):
+    """"r = infinity": radii 1, 2, ... (order as in hasf) until the first
+    radius that leaves the set unchanged, at most r_max (0: the saturation
+    radius, the least i with i^2 >= (H-1)^2 + (W-1)^2). Returns (result,
+    last radius applied)."""
+    x = np.ascontiguousarray(X, dtype=np.uint8).copy()
+    c, cp = _opt_u8(C)
+    d, dp = _opt_u8(D)
+    used = ctypes.c_int(0)
+    _check(_load().oracle_hasf_inf(x.ctypes.data_as(U8P), cp, dp, x.shape[0], x.shape[1], n, order, r_max,
+                                   ctypes.byref(used)), "hasf_inf")
+    return x, used.value
 
 
 def hasf_labels(Lab, values, r: int):

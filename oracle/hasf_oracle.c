@@ -710,6 +710,67 @@ long oracle_hasf_order(uint8_t* X, const uint8_t* C, const uint8_t* D, int H, in
     return hasf_core(X, C, D, H, W, r, n, order, stages, sched_subfield);
 }
 
+/* "r = infinity" (the column of Tab. 1, which the paper does not define):
+ * radii i = 1, 2, ... as in oracle_hasf_order, stopping after the first
+ * radius whose cutting and filling leave X unchanged, and at the latest after
+ * radius r_max (r_max <= 0: the saturation radius, the least i with
+ * i^2 >= (H-1)^2 + (W-1)^2; from there on every threshold and every level
+ * test of a radius holds for all pixels, so every larger radius applies the
+ * same operator). C <- C n X and D <- D \ X from the input, as for a finite
+ * radius. *r_used receives the last radius applied (at least 1). */
+long oracle_hasf_inf(uint8_t* X, const uint8_t* C, const uint8_t* D, int H, int W, int n, int order, int r_max,
+                     int* r_used)
+{
+    if (H < 1 || W < 1 || (n != 8 && n != 4) || (order != 0 && order != 1) || !r_used)
+        return ORACLE_EINVAL;
+    const size_t N = (size_t)H * W;
+    normalise(X, N);
+    int cap = r_max;
+    if (cap <= 0) {
+        const long long far = (long long)(H - 1) * (H - 1) + (long long)(W - 1) * (W - 1);
+        cap = 1;
+        while ((long long)cap * cap < far)
+            ++cap;
+    }
+    uint8_t* Cn = (uint8_t*)malloc(N);
+    uint8_t* Dn = (uint8_t*)malloc(N);
+    uint8_t* prev = (uint8_t*)malloc(N);
+    if (!Cn || !Dn || !prev) {
+        free(Cn); free(Dn); free(prev);
+        return ORACLE_ENOMEM;
+    }
+    for (size_t p = 0; p < N; ++p) {
+        Cn[p] = C && C[p] && X[p];
+        Dn[p] = D && D[p] && !X[p];
+    }
+    work_t w;
+    long rc = work_alloc(&w, N, sched_subfield);
+    if (rc) {
+        free(Cn); free(Dn); free(prev);
+        return rc;
+    }
+    w.lut = lut_for(n);
+    *r_used = 0;
+    for (int i = 1; i <= cap && rc == 0; ++i) {
+        memcpy(prev, X, N);
+        if (order == 0) {
+            rc = hc(X, C ? Cn : NULL, H, W, i, &w, NULL);
+            if (rc == 0)
+                rc = hf(X, D ? Dn : NULL, H, W, i, &w, NULL);
+        } else {
+            rc = hf(X, D ? Dn : NULL, H, W, i, &w, NULL);
+            if (rc == 0)
+                rc = hc(X, C ? Cn : NULL, H, W, i, &w, NULL);
+        }
+        *r_used = i;
+        if (rc == 0 && memcmp(prev, X, N) == 0)
+            break;
+    }
+    work_free(&w);
+    free(Cn); free(Dn); free(prev);
+    return rc < 0 ? rc : 0;
+}
+
 /* The same filter with the queue-ordered schedule below. */
 long oracle_hasf_queue(uint8_t* X, const uint8_t* C, int H, int W, int r)
 {

@@ -347,3 +347,26 @@ def hasf_composed(X, C, D, r: int, n: int = 8, order: int = 0):
             st += [a, x]
         out.append(np.stack(st))
     return np.stack(out) if out else np.zeros((0, 4) + X.shape, np.uint8)
+
+
+def hasf_inf_composed(X, C, D, n: int = 8, order: int = 0, r_max: int = 0):
+    """"r = infinity" from the parts above: radii 1, 2, ... until the first
+    radius that leaves the set unchanged, at most r_max (0: the least i with
+    i^2 >= (H-1)^2 + (W-1)^2, past which the thresholds and level tests of a
+    radius no longer depend on it). Returns (result, last radius applied)."""
+    x = (np.asarray(X) != 0).astype(np.uint8)
+    H, W = x.shape
+    Cn = None if C is None else ((np.asarray(C) != 0) & (x != 0))
+    Dn = None if D is None else ((np.asarray(D) != 0) & (x == 0))
+    cap = r_max if r_max > 0 else int(np.ceil(np.sqrt((H - 1) ** 2 + (W - 1) ** 2 - 1e-9)))
+    cap = max(cap, 1)
+    table = simple_table(n)
+    i = 0
+    for i in range(1, cap + 1):
+        prev = x
+        for op in (("c", "f") if order == 0 else ("f", "c")):
+            x = hc_composed(x, Cn, i, table)[1] if op == "c" else hf_composed(x, Dn, i, table)[1]
+        x = x.astype(np.uint8)
+        if np.array_equal(x, prev):
+            break
+    return x, i
