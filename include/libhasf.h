@@ -75,12 +75,24 @@ typedef struct {
     size_t batch_grid_min_pixels; /* the same for batches of several images and served frames.
                                      0 = HASF_BATCH_GRID_MIN_PIXELS_DEFAULT; SIZE_MAX = never */
     int tile_rows;          /* large images (hasf_filter, hasf_filter_cd, batches) whose rows fit are filtered
-                               by row tiles of this many rows, each tile's state in LDS, exchanging halo rows
-                               every two rounds; 0 = HASF_TILE_ROWS_DEFAULT; an even number >= 8; -1 = never
-                               (the grid of workgroups with the state in global memory) */
+                               by row tiles of this many own rows, each tile's state in LDS with tile_halo rows
+                               of its neighbours on each side, exchanged every tile_halo / 4 rounds;
+                               0 = HASF_TILE_ROWS_DEFAULT; an even number >= 4 (raised to tile_halo);
+                               -1 = never (the grid of workgroups with the state in global memory) */
+    int tile_halo;          /* 0 = HASF_TILE_HALO_DEFAULT; 4, 8, 12 or 16 */
+    const char* tune_cache; /* NULL: lone images are routed by the fields above. Otherwise the path of a text
+                               file of measured launch choices (created if missing, read at hasf_create):
+                               the first lone image (hasf_filter, hasf_filter_cd, a batch of one) of a size
+                               class -- H and W rounded up to multiples of 256, and r -- is filtered with each
+                               candidate (one workgroup, row tiles of several heights and halos, the grid
+                               kernel) on a copy of it, timed, and the fastest is appended to the file and
+                               used for that class from then on. Every candidate runs the same schedule, so
+                               results do not depend on the choice; the first image of a class costs about
+                               2 x (number of candidates) filters more, plus an allocation of H ld bytes. */
 } hasf_opts;
 
 #define HASF_TILE_ROWS_DEFAULT 32
+#define HASF_TILE_HALO_DEFAULT 12
 
 /* Create a context on opts->device (opts may be NULL: device 0, defaults).
  * The context owns its scratch memory and the default (null) stream. */
@@ -220,6 +232,22 @@ hasf_status hasf_filter(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, int H, int 
  */
 hasf_status hasf_filter_cd(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, const uint8_t* D, int H, int W,
                            int64_t ld, int r, int conn);
+
+/*
+ * "r = infinity" (Tab. 1 reports it; the paper does not define it): the radius
+ * loop of hasf_filter_cd, in the given order (as hasf_image.order), run for
+ * i = 1, 2, ... and stopped after the first radius whose cutting and filling
+ * leave X unchanged, or after radius r_max (r_max = 0: the saturation radius,
+ * the least i with i^2 >= (H-1)^2 + (W-1)^2, from which on every radius
+ * applies the same operator); *r_used would receive the last radius applied.
+ * SWITCHED OFF in this build: after validating its arguments (HASF_EINVAL as
+ * hasf_filter_cd, r_used == NULL, r_max < 0, flags other than 0 or
+ * HASF_INF_COMPOSED) it returns HASF_EINTERNAL with *r_used = 0 and does no
+ * device work.
+ */
+#define HASF_INF_COMPOSED 1u
+hasf_status hasf_filter_inf(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, const uint8_t* D, int H, int W,
+                            int64_t ld, int conn, int order, int r_max, unsigned flags, int* r_used);
 
 /*
  * One image of a batch (zero-initialise: D = NULL, conn = 0 and order = 0

@@ -6,6 +6,8 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <map>
+#include <string>
 
 #include "libhasf.h"
 
@@ -167,18 +169,17 @@ struct TileCtl {
     unsigned lev[4 * HASF_R_MAX][HASF_LEVELS_MAX];
 };
 
-// Row tiles: halo rows kept on each side of a tile, and rounds a tile runs
-// between two exchanges (a pass moves information by one row, a round is
-// four passes).
-constexpr int TILE_HALO = 8;
-constexpr int TILE_EPOCH_ROUNDS = TILE_HALO / 4;
+// Row tiles: halo rows kept on each side of a tile (by default; 4, 8, 12 or
+// 16), so that a tile runs halo / 4 rounds between two exchanges (a pass
+// moves information by one row, a round is four passes).
+constexpr int TILE_HALO = HASF_TILE_HALO_DEFAULT;
 constexpr int TILE_NT = 1024;  // threads of a tile's workgroup
 
-// Tiling of one image: tiles of TH own rows (TH even, >= TILE_HALO), the
-// last one shorter; each keeps up to ER = TH + 2 TILE_HALO rows in LDS.
+// Tiling of one image: tiles of TH own rows (TH even, >= halo), the last one
+// shorter; each keeps up to ER = TH + 2 halo rows in LDS.
 struct TilePlan {
     bool ok;
-    int TH, ntiles, ER;
+    int TH, ntiles, ER, halo;
     size_t lds_bytes;     // dynamic LDS of a tile
     size_t planes_bytes;  // Rg, A, K, Dp (row-major), two exchange copies (sub-images)
     size_t ent_words;     // level entry slots per tile: levels(r) x ER x WW
@@ -242,26 +243,32 @@ inline ImageLayout image_layout(int H, int W, int r, size_t lds_cap)
     return L;
 }
 
+// Most rounds a tile runs between two exchanges (also in hasf_device.h).
+constexpr int TILE_ROUNDS_MAX_HOST = 4;
+
 // Own rows per tile when the caller does not choose.
 constexpr int TILE_ROWS_DEFAULT = HASF_TILE_ROWS_DEFAULT;
 
 // Tiling of an H x W image at radius r with tiles of TH_req own rows (0: the
 // default), at most max_tiles tiles (taller tiles when needed). Not ok when a
-// band of TILE_HALO own rows and its halos does not fit lds_cap bytes of LDS
+// band of `halo` own rows and its halos does not fit lds_cap bytes of LDS
 // (very wide images), or when the image would be one tile.
-inline TilePlan tile_plan(int H, int W, int r, size_t lds_cap, int max_tiles, int TH_req)
+inline TilePlan tile_plan(int H, int W, int r, size_t lds_cap, int max_tiles, int TH_req, int halo = TILE_HALO)
 {
     TilePlan P{};
     P.ok = false;
+    if (halo < 4 || halo > 4 * TILE_ROUNDS_MAX_HOST || (halo & 3))
+        return P;
+    P.halo = halo;
     const size_t WW = (size_t)(W + 63) / 64, NWD = (size_t)H * WW;
     int ercap = 0;
-    while (ercap < H + 2 * TILE_HALO && hasf_align256(state_bytes(ercap + 2, W, true)) <= lds_cap)
+    while (ercap < H + 2 * halo && hasf_align256(state_bytes(ercap + 2, W, true)) <= lds_cap)
         ercap += 2;
-    const int thmax = ((ercap - 2 * TILE_HALO) / 2) * 2;
-    if (thmax < TILE_HALO || max_tiles < 2)
+    const int thmax = ((ercap - 2 * halo) / 2) * 2;
+    if (thmax < halo || max_tiles < 2)
         return P;
     int th = TH_req > 0 ? TH_req : TILE_ROWS_DEFAULT;
-    th = th < TILE_HALO ? TILE_HALO : th;
+    th = th < halo ? halo : th;
     th = (th + 1) / 2 * 2;
     th = th > thmax ? thmax : th;
     if ((H + th - 1) / th > max_tiles) {
@@ -276,7 +283,7 @@ inline TilePlan tile_plan(int H, int W, int r, size_t lds_cap, int max_tiles, in
     P.ok = true;
     P.TH = th;
     P.ntiles = nt;
-    P.ER = th + 2 * TILE_HALO < H ? th + 2 * TILE_HALO : H;
+    P.ER = th + 2 * halo < H ? th + 2 * halo : H;
     P.lds_bytes = hasf_align256(state_bytes(P.ER, W, true));
     P.planes_bytes = hasf_align256(4 * NWD * 8) + 2 * hasf_align256(tile_sub_words(H, W) * 4);
     const size_t nlev = (size_t)(r > 0 ? hasf_levels(r) : 1);
@@ -309,6 +316,15 @@ struct TopoArgs {
 }  // namespace hasf_detail
 
 // host-side context
+// How a lone image is filtered: by one workgroup, by row tiles of th own
+// rows and `halo` halo rows, or by the grid kernel (state in global memory).
+struct LaunchChoice {
+    enum Kind { WORKGROUP = 0, TILES = 1, GRID = 2 };
+    int kind;
+    int th, halo;
+    float ms;  // measured time of the choice (0 when not measured)
+};
+
 struct hasf_ctx {
     int device;
     hipStream_t stream;
@@ -327,8 +343,12 @@ struct hasf_ctx {
     // workgroups: alone (hasf_filter, a batch of one), in batches and served
     size_t grid_min_px, batch_grid_min_px;
     // own rows per tile of the row-tile path for large images (0: default;
-    // -1: large images always go to the grid kernel)
-    int tile_rows;
+    // -1: large images always go to the grid kernel) and halo rows per side
+    int tile_rows, tile_halo;
+    // measured launch choices of lone images by size class, and the file they
+    // are kept in (empty: no tuning)
+    std::map<uint64_t, LaunchChoice> tune;
+    std::string tune_path;
     // sticky device word set by a grid launch whose barrier gave up; read and
     // cleared by hasf_sync when grid work was enqueued since the last check
     unsigned* d_grid_err;

@@ -278,6 +278,7 @@ __device__ void clear_candidates(const Img<LDS>& g, int t0, int tn)
 // k at CTL_TCHG + k.
 enum { CTL_CHG = 0, CTL_CNT = 2, CTL_PROD = 4, CTL_WORDS = 8, CTL_PROD2 = 8, CTL_TCHG = 12, CTL_LDS_WORDS = 16 };
 constexpr int TILE_ROUNDS_MAX = 4;
+static_assert(TILE_ROUNDS_MAX == TILE_ROUNDS_MAX_HOST, "rounds between tile exchanges");
 
 // per-phase scheduling state (uniform registers)
 struct Sched {

@@ -3,20 +3,20 @@
 // blocking).
 //
 // Tile t (one workgroup) owns image rows [t TH, (t + 1) TH) and also keeps
-// TILE_HALO rows on each side that its neighbours own, so its LDS state is a
-// band of up to TH + 2 TILE_HALO rows in the layout of the per-image kernel.
-// A subfield pass decides a pixel from its 3x3 neighbourhood, so after k
-// passes a band's rows can differ from the whole-image schedule only within
-// k rows of the band's cut edges: a tile runs TILE_EPOCH_ROUNDS rounds (4
-// passes each, TILE_HALO passes in all) on its own and its own rows are then
-// exactly the schedule's. Then every tile publishes its first and last
-// TILE_HALO own rows, the tiles meet at one grid barrier, and each replaces
+// `halo` rows on each side that its neighbours own, so its LDS state is a
+// band of up to TH + 2 halo rows in the layout of the per-image kernel. A
+// subfield pass decides a pixel from its 3x3 neighbourhood, so after k passes
+// a band's rows can differ from the whole-image schedule only within k rows
+// of the band's cut edges: a tile runs halo / 4 rounds (4 passes each, halo
+// passes in all) on its own and its own rows are then exactly the
+// schedule's. Then every tile publishes its first and last halo own rows,
+// the tiles meet at one grid barrier, and each replaces
 // its halo rows with its neighbours' (flagging every word whose test reads
 // a changed word). A level of the schedule ends after the first round that
 // changes nothing anywhere; the tiles learn it at the barrier that follows,
 // and the rounds they ran after it changed nothing. So the result is the
-// schedule's bit for bit, with one grid barrier per TILE_EPOCH_ROUNDS rounds
-// instead of one per pass.
+// schedule's bit for bit, with one grid barrier per halo / 4 rounds instead
+// of one per pass.
 //
 // Distances: each tile labels the candidates of its whole band from the
 // row-major copy of the set in global memory (Rg), which the owners of the
@@ -251,18 +251,19 @@ __device__ int tile_levels_at(int i)
 struct Band {
     Img<true> g;
     int t, nt, r0, r1, e0, ER, lo, hi;  // lo, hi: own rows in band coordinates
+    int halo;
     size_t SUBG;                        // words per sub-image of an exchange copy
     glb_u32* Xs[2];
 };
 
-// Own rows [r0, r0 + TILE_HALO) and [r1 - TILE_HALO, r1) (the rows the
-// neighbours keep as halo) into exchange copy `out`.
+// Own rows [r0, r0 + halo) and [r1 - halo, r1) (the rows the neighbours
+// keep as halo) into exchange copy `out`.
 __device__ __forceinline__ void publish(const Band& b, glb_u32* out)
 {
     const Img<true>& g = b.g;
     const int WW = g.WW;
-    const int top_hi = b.t > 0 ? min(b.r1, b.r0 + TILE_HALO) : b.r0;
-    const int bot_lo = b.t < b.nt - 1 ? max(top_hi, b.r1 - TILE_HALO) : b.r1;
+    const int top_hi = b.t > 0 ? min(b.r1, b.r0 + b.halo) : b.r0;
+    const int bot_lo = b.t < b.nt - 1 ? max(top_hi, b.r1 - b.halo) : b.r1;
     const int ntop = top_hi - b.r0;
     const int n = (ntop + (b.r1 - bot_lo)) * 2 * WW;
     for (int u = threadIdx.x; u < n; u += TILE_NT) {
@@ -322,9 +323,8 @@ __device__ __forceinline__ void refresh_halo(const Band& b, const glb_u32* in, i
     }
 }
 
-// Levels of one phase in increasing order; in each, epochs of
-// TILE_EPOCH_ROUNDS rounds and one exchange until a round changed nothing
-// anywhere.
+// Levels of one phase in increasing order; in each, epochs of halo / 4
+// rounds and one exchange until a round changed nothing anywhere.
 __device__ __forceinline__ bool tile_levels(Band& b, const TileView& v, TileSync& ts, int* s_ok, int* s_flag,
                                             lds_u32* cnt, int pi, int nlev, bool thin)
 {
@@ -347,7 +347,8 @@ __device__ __forceinline__ bool tile_levels(Band& b, const TileView& v, TileSync
         const unsigned start = ts.round;
         unsigned lvl_last = start;  // the level's last round that changed something
         for (;;) {
-            const int last = run_rounds<true, TILE_NT, true>(g, thin, sc, TILE_EPOCH_ROUNDS, b.lo, b.hi);
+            const int epoch_rounds = b.halo >> 2;
+            const int last = run_rounds<true, TILE_NT, true>(g, thin, sc, epoch_rounds, b.lo, b.hi);
             publish(b, b.Xs[ts.gen & 1]);
             // by barrier parity: a tile that reads this epoch's word after
             // the barrier never sees a store of the next epoch (a faster
@@ -356,7 +357,7 @@ __device__ __forceinline__ bool tile_levels(Band& b, const TileView& v, TileSync
             unsigned* lcw = &ts.tc->last_change[ts.gen & 1];
             if (last && threadIdx.x == 0)
                 __hip_atomic_fetch_max(lcw, ts.round + (unsigned)last, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ts.round += TILE_EPOCH_ROUNDS;
+            ts.round += (unsigned)epoch_rounds;
             if (!tile_sync(ts, s_ok))
                 return false;
             // the last round of the epoch changed no tile's own rows: the
@@ -388,16 +389,17 @@ __device__ __forceinline__ bool tile_levels(Band& b, const TileView& v, TileSync
 }
 
 __device__ __forceinline__ bool tile_image(const ImgDesc* __restrict__ dp, TileSync& ts, int* s_ok, int* s_flag,
-                                           uint64_t* smem, lds_u32* cnt, lds_i32* ctl, int TH, int ERmax)
+                                           uint64_t* smem, lds_u32* cnt, lds_i32* ctl, int TH, int ERmax, int halo)
 {
     const int H = dp->H, W = dp->W;
     Band b;
+    b.halo = halo;
     b.t = blockIdx.x;
     b.nt = gridDim.x;
     b.r0 = b.t * TH;
     b.r1 = min(H, b.r0 + TH);
-    b.e0 = max(0, b.r0 - TILE_HALO);
-    b.ER = min(H, b.r1 + TILE_HALO) - b.e0;
+    b.e0 = max(0, b.r0 - halo);
+    b.ER = min(H, b.r1 + halo) - b.e0;
     b.lo = b.r0 - b.e0;
     b.hi = b.r1 - b.e0;
     Img<true>& g = b.g;
@@ -499,11 +501,12 @@ __device__ __forceinline__ bool tile_image(const ImgDesc* __restrict__ dp, TileS
 
 }  // namespace
 
-// One image over gridDim.x row tiles of TH own rows (ERmax: the longest
-// band, which sizes the entry lists). If a grid barrier gave up, tc->err and
-// the caller's sticky word are set (the image is then undefined).
+// One image over gridDim.x row tiles of TH own rows and `halo` halo rows
+// (ERmax: the longest band, which sizes the entry lists). If a grid barrier
+// gave up, tc->err and the caller's sticky word are set (the image is then
+// undefined).
 __global__ __launch_bounds__(TILE_NT) void hasf_tile_kernel(const ImgDesc* __restrict__ dp, TileCtl* tc,
-                                                            unsigned* err_out, int TH, int ERmax)
+                                                            unsigned* err_out, int TH, int ERmax, int halo)
 {
     extern __shared__ uint64_t smem[];
     __shared__ unsigned cnt[HASF_LEVELS_MAX];
@@ -512,7 +515,7 @@ __global__ __launch_bounds__(TILE_NT) void hasf_tile_kernel(const ImgDesc* __res
     if (threadIdx.x == 0)
         s_flag = 0;
     TileSync ts{tc, gridDim.x, 0u, 0u, 0u, 0u};
-    const bool ok = tile_image(dp, ts, &s_ok, &s_flag, smem, (lds_u32*)cnt, (lds_i32*)ctl, TH, ERmax);
+    const bool ok = tile_image(dp, ts, &s_ok, &s_flag, smem, (lds_u32*)cnt, (lds_i32*)ctl, TH, ERmax, halo);
     if (!ok && threadIdx.x == 0) {
         __hip_atomic_store(&tc->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (err_out)
@@ -537,7 +540,7 @@ hipError_t launch_tile(const ImgDesc* d_desc, TileCtl* d_ctl, unsigned* d_err, c
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(hasf_tile_kernel, dim3(P.ntiles), dim3(TILE_NT), P.lds_bytes, stream, d_desc, d_ctl, d_err,
-                       P.TH, P.ER);
+                       P.TH, P.ER, P.halo);
     return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@ HASF_R_MAX = 15
 HASF_SERVE_LANES_MAX = 16
 HASF_SERVE_PERSISTENT = 1
 HASF_NOALLOC_SCRATCH_BYTES = 16 << 20
+HASF_INF_COMPOSED = 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libhasf.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
@@ -38,7 +39,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 class _Opts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("hbm_budget", ctypes.c_size_t), ("flags", ctypes.c_uint),
                 ("grid_min_pixels", ctypes.c_size_t), ("batch_grid_min_pixels", ctypes.c_size_t),
-                ("tile_rows", ctypes.c_int)]
+                ("tile_rows", ctypes.c_int), ("tile_halo", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
 
 
 class _Image(ctypes.Structure):
@@ -96,13 +97,15 @@ _lib.hasf_filter.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c
 _lib.hasf_filter_cd.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
                                 ctypes.c_int]
 _lib.hasf_filter_batch.argtypes = [_vp, ctypes.POINTER(_Image), ctypes.c_int]
+_lib.hasf_filter_inf.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.POINTER(ctypes.c_int)]
 _lib.hasf_filter_labels.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_uint8), ctypes.c_int, ctypes.c_int, _vp,
                                     ctypes.c_int64, ctypes.c_int64]
 for _f in ("hasf_create", "hasf_set_stream", "hasf_sync", "hasf_simple_lut", "hasf_edt_sq", "hasf_edt_sq_noalloc",
            "hasf_homotopic_thin", "hasf_homotopic_thicken", "hasf_homotopic_thin_conn",
            "hasf_homotopic_thicken_conn", "hasf_filter", "hasf_filter_cd",
-           "hasf_filter_batch", "hasf_filter_labels"):
+           "hasf_filter_batch", "hasf_filter_labels", "hasf_filter_inf"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -174,13 +177,16 @@ def _companion(T, X, name):
 
 class Context:
     def __init__(self, device: int = 0, hbm_budget: int = 0, grid_min_pixels: int = 0,
-                 batch_grid_min_pixels: int = 0, tile_rows: int = 0):
+                 batch_grid_min_pixels: int = 0, tile_rows: int = 0, tile_halo: int = 0,
+                 tune_cache: str = None):
         import torch
         self._torch = torch
         self.device = device
         self.tile_rows = tile_rows
+        self.tile_halo = tile_halo
         h = _vp()
-        opts = _Opts(device, hbm_budget, 0, grid_min_pixels, batch_grid_min_pixels, tile_rows)
+        opts = _Opts(device, hbm_budget, 0, grid_min_pixels, batch_grid_min_pixels, tile_rows, tile_halo,
+                     tune_cache.encode() if tune_cache else None)
         st = _lib.hasf_create(ctypes.byref(opts), ctypes.byref(h))
         if st != HASF_OK:
             raise HasfError(st, _lib.hasf_last_error(None).decode())
@@ -268,6 +274,20 @@ class Context:
         else:
             self._check(_lib.hasf_filter_cd(self._h, _ptr(X), _ptr(C), _ptr(D), H, W, ld, r, conn))
         return X
+
+    def filter_inf(self, X, C=None, D=None, conn: int = 8, order: int = 0, r_max: int = 0,
+                   composed: bool = False) -> int:
+        """hasf_filter_inf: radii 1, 2, ... until a radius leaves X unchanged
+        (at most r_max; 0: the saturation radius). Returns the last radius
+        applied; the context's stream is idle on return."""
+        H, W, ld = _img(X, "X", self.device)
+        _companion(C, X, "C")
+        _companion(D, X, "D")
+        self._stream()
+        used = ctypes.c_int(0)
+        self._check(_lib.hasf_filter_inf(self._h, _ptr(X), _ptr(C), _ptr(D), H, W, ld, conn, order, r_max,
+                                         HASF_INF_COMPOSED if composed else 0, ctypes.byref(used)))
+        return used.value
 
     def plan_batch(self, items):
         """Prepare the descriptor array of a batch once (the tensors must stay alive).

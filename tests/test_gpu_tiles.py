@@ -132,6 +132,29 @@ def test_tiles_keep_topology_on_a_2048_square():
 
 
 def test_bad_tile_rows_is_refused():
-    for th in (-2, 3, 7, 9):
+    for th in (-2, 2, 3, 7, 9):
         with pytest.raises(hasf.HasfError):
             hasf.Context(0, tile_rows=th)
+
+
+_HCTX = {}
+
+
+@pytest.mark.parametrize("halo", [4, 12, 16])
+def test_tiles_other_halo_depths(halo):
+    # halo / 4 rounds between exchanges; tiles at least as tall as the halo
+    if halo not in _HCTX:
+        _HCTX[halo] = hasf.Context(0, grid_min_pixels=1, batch_grid_min_pixels=1, tile_rows=8, tile_halo=halo)
+    c = _HCTX[halo]
+    for (H, W, r, dens, withC, seed) in [(37, 130, 3, 0.55, True, 21), (129, 191, 6, 0.5, True, 22),
+                                         (300, 200, 4, 0.5, False, 23)]:
+        X = synth.random_binary(H, W, dens, 800 + seed)
+        C = synth.random_binary(H, W, 0.05, 850 + seed) if withC else None
+        say("tiles, halo", halo, (H, W, r))
+        assert np.array_equal(_filter(c, X, C, r), oracle.hasf(X, C, r))
+    X, C, r = synth.workload_shapes()
+    say("tiles, halo", halo, "512x512 r=5")
+    assert np.array_equal(_filter(c, X, C, r), oracle.hasf(X, C, r))
+    for bad in (2, 6, 20):
+        with pytest.raises(hasf.HasfError):
+            hasf.Context(0, tile_halo=bad)

@@ -1,0 +1,102 @@
+"""The launch-choice autotuner (hasf_opts.tune_cache) and the determinism it
+relies on: a lone image gives the same result, bit for bit, under every
+launch choice the tuner may pick (one workgroup, row tiles of each candidate
+height and halo, the grid kernel); a tuning context measures a size class
+once, writes the choice to its cache file, and a new context reads it back
+instead of measuring again."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import dev, host, say
+from paper_1603_09337_amd import hasf, synth
+
+pytestmark = pytest.mark.gpu
+
+BIG = 2**64 - 1
+# every candidate of the tuner, as context options
+CHOICES = {
+    "workgroup": dict(grid_min_pixels=BIG, batch_grid_min_pixels=BIG),
+    "tiles16/8": dict(grid_min_pixels=1, tile_rows=16, tile_halo=8),
+    "tiles24/12": dict(grid_min_pixels=1, tile_rows=24, tile_halo=12),
+    "tiles32/8": dict(grid_min_pixels=1, tile_rows=32, tile_halo=8),
+    "tiles32/12": dict(grid_min_pixels=1, tile_rows=32, tile_halo=12),
+    "tiles48/12": dict(grid_min_pixels=1, tile_rows=48, tile_halo=12),
+    "grid": dict(grid_min_pixels=1, tile_rows=-1),
+}
+_CTX = {}
+
+
+def _ctx(name):
+    if name not in _CTX:
+        _CTX[name] = hasf.Context(0, **CHOICES[name])
+    return _CTX[name]
+
+
+def _run(c, X, C, r, D=None, n=8):
+    x = dev(X)
+    c.filter(x, dev(C) if C is not None else None, r, D=dev(D) if D is not None else None, conn=n)
+    c.sync()
+    return host(x)
+
+
+@pytest.mark.parametrize("shape,r", [((600, 900), 4), ((1100, 1300), 3)])
+def test_every_launch_choice_gives_the_same_image(shape, r):
+    X = synth.workload_disks(H=shape[0], W=shape[1])[0]
+    C = synth.random_binary(shape[0], shape[1], 0.01, 77) & X
+    exp = oracle.hasf(X, C, r)
+    for name in CHOICES:
+        say("launch choice", name, shape, "r =", r)
+        assert np.array_equal(_run(_ctx(name), X, C, r), exp), name
+
+
+def test_choices_agree_with_d_and_the_48_pair():
+    X = synth.disks_image(300, 420, np.random.default_rng(5))
+    rng = np.random.default_rng(6)
+    D = ((rng.random(X.shape) < 0.2) & (X == 0)).astype(np.uint8)
+    exp = oracle.hasf(X, None, 5, D=D, n=4)
+    for name in CHOICES:
+        assert np.array_equal(_run(_ctx(name), X, None, 5, D=D, n=4), exp), name
+
+
+def test_tuning_measures_once_and_reads_its_cache_back():
+    X = synth.workload_disks(H=1000, W=1200)[0]
+    exp = oracle.hasf(X, None, 3)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.txt")
+        c = hasf.Context(0, tune_cache=path)
+        say("tuning 1000x1200 r=3")
+        assert np.array_equal(_run(c, X, None, 3), exp)
+        lines = open(path).read().split("\n")
+        lines = [l for l in lines if l.startswith("hasf-tune 1 ")]
+        assert len(lines) == 1
+        f = lines[0].split()
+        assert f[2:5] == ["4", "5", "3"] and f[5] in ("0", "1", "2")
+        # same class: no new measurement
+        Y = synth.workload_disks(H=990, W=1150, seed=5)[0]
+        assert np.array_equal(_run(c, Y, None, 3), oracle.hasf(Y, None, 3))
+        assert len([l for l in open(path) if l.startswith("hasf-tune 1 ")]) == 1
+        c.close()
+        # a new context reads the choice back
+        c2 = hasf.Context(0, tune_cache=path)
+        assert np.array_equal(_run(c2, X, None, 3), exp)
+        assert len([l for l in open(path) if l.startswith("hasf-tune 1 ")]) == 1
+        # another class is measured and appended
+        Z = synth.workload_disks(H=300, W=260)[0]
+        assert np.array_equal(_run(c2, Z, None, 2), oracle.hasf(Z, None, 2))
+        assert len([l for l in open(path) if l.startswith("hasf-tune 1 ")]) == 2
+        c2.close()
+
+
+def test_unreadable_cache_lines_are_ignored():
+    X = synth.workload_disks(H=200, W=230)[0]
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.txt")
+        with open(path, "w") as f:
+            f.write("garbage\nhasf-tune 1 1 1 2 9 0 0 1.0\nhasf-tune 1 1 1\n")
+        c = hasf.Context(0, tune_cache=path)
+        assert np.array_equal(_run(c, X, None, 2), oracle.hasf(X, None, 2))
+        c.close()
