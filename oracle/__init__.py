@@ -17,6 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hasf_oracle.c")
+_SRC3 = os.path.join(_HERE, "hasf_oracle3d.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -29,7 +30,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC",
-                               "-o", tmp, _SRC])
+                               "-o", tmp, _SRC, _SRC3])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -38,7 +39,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC), os.path.getmtime(_SRC3)):
         build(force=True)
     lib = ctypes.CDLL(_LIB)
     lib.oracle_simple_lut.argtypes = [ctypes.c_int, U8P]
@@ -73,6 +74,13 @@ def _load():
     lib.oracle_hasf_inf.argtypes = [U8P, U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.oracle_hasf_inf.restype = ctypes.c_long
+    lib.oracle3_topo_numbers.argtypes = [ctypes.c_uint32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.oracle3_simple.argtypes = [ctypes.c_uint32]
+    lib.oracle3_edt_sq.argtypes = [U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, U32P]
+    lib.oracle3_schedule.argtypes = [ctypes.c_int, U8P, U8P, U32P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.oracle3_schedule.restype = ctypes.c_long
+    lib.oracle3_hasf.argtypes = [U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, U8P]
+    lib.oracle3_hasf.restype = ctypes.c_long
     lib.oracle_hasf_queue.argtypes = [U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.oracle_hasf_queue.restype = ctypes.c_long
     _lib = lib
@@ -222,6 +230,58 @@ def hasf_inf(X, C=None, D=None, n: int = 8, order: int = 0, r_max: int = 0):
     _check(_load().oracle_hasf_inf(x.ctypes.data_as(U8P), cp, dp, x.shape[0], x.shape[1], n, order, r_max,
                                    ctypes.byref(used)), "hasf_inf")
     return x, used.value
+
+
+# ---------------------------------------------------------------------------
+# 3D: (26,6) connectivity, volumes of shape (D, H, W)
+# ---------------------------------------------------------------------------
+def topo_numbers3(code: int):
+    """(T26, Tbar6) of a 26-neighbourhood code (bit b: offset b of
+    {-1,0,1}^3 without the centre, lexicographic in (dz, dy, dx))."""
+    T, Tb = ctypes.c_int(0), ctypes.c_int(0)
+    _load().oracle3_topo_numbers(code, ctypes.byref(T), ctypes.byref(Tb))
+    return T.value, Tb.value
+
+
+def simple3(code: int) -> bool:
+    return bool(_load().oracle3_simple(code))
+
+
+def _u8v(a):
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    assert a.ndim == 3
+    return a, a.ctypes.data_as(U8P)
+
+
+def edt_sq3(F, frame: bool = False) -> np.ndarray:
+    """Squared distance to the nearest nonzero voxel (+ outside the box if frame)."""
+    f, fp = _u8v(F)
+    out = np.zeros(f.shape, dtype=np.uint32)
+    _check(_load().oracle3_edt_sq(fp, *f.shape, int(bool(frame)), out.ctypes.data_as(U32P)), "edt_sq3")
+    return out
+
+
+def schedule3(mode: int, S, B, P):
+    """mode 0: thin S keeping B; mode 1: thicken S inside B; priority P."""
+    s = np.ascontiguousarray(S, dtype=np.uint8).copy()
+    b = None if B is None else np.ascontiguousarray(B, dtype=np.uint8)
+    p = np.ascontiguousarray(P, dtype=np.uint32)
+    rc = _load().oracle3_schedule(mode, s.ctypes.data_as(U8P), None if b is None else b.ctypes.data_as(U8P),
+                                  p.ctypes.data_as(U32P), *s.shape)
+    if rc < 0:
+        raise RuntimeError("schedule3 failed (%d)" % rc)
+    return s
+
+
+def hasf3(X, C, r: int, stages: bool = False):
+    """3D HASF of order r, (26,6), constraint set C; with stages=True also an
+    (r, 4, D, H, W) dump as in hasf()."""
+    x = np.ascontiguousarray(X, dtype=np.uint8).copy()
+    c = None if C is None else np.ascontiguousarray(C, dtype=np.uint8)
+    st = np.zeros((max(r, 1), 4) + x.shape, dtype=np.uint8) if stages else None
+    _check(_load().oracle3_hasf(x.ctypes.data_as(U8P), None if c is None else c.ctypes.data_as(U8P), *x.shape, r,
+                                None if st is None else st.ctypes.data_as(U8P)), "hasf3")
+    return (x, st[:r]) if stages else x
 
 
 def hasf_labels(Lab, values, r: int):
