@@ -55,9 +55,10 @@ typedef enum {
 typedef struct hasf_ctx hasf_ctx;
 
 /* Defaults of hasf_opts.grid_min_pixels and hasf_opts.batch_grid_min_pixels.
- * A lone image of up to about 1.4 Mpx is filtered faster by one workgroup
- * than by a grid of them (both measured at r = 3, 5, 8). */
-#define HASF_GRID_MIN_PIXELS_DEFAULT (((size_t)1 << 20) + ((size_t)3 << 17))
+ * A lone image of up to about 512 x 512 is filtered faster by one workgroup
+ * than by row tiles; from 768 x 768 on the tiles take less than half the time
+ * (measured at r = 2, 5, 8). */
+#define HASF_GRID_MIN_PIXELS_DEFAULT ((size_t)1 << 19)
 #define HASF_BATCH_GRID_MIN_PIXELS_DEFAULT ((size_t)1 << 23)
 
 /*
@@ -163,7 +164,8 @@ hasf_status hasf_edt_sq(hasf_ctx* ctx, const uint8_t* feat, int H, int W, int64_
  * the same transform, the same kernels and the same arguments and results,
  * but it calls no hipMalloc, hipFree or other allocating routine. Its
  * scratch (per 32-row segment and column: a feature mask and the nearest
- * feature rows above and below, ceil(H / 32) * W * 12 + 768 bytes) lives in
+ * feature rows above and below; a list of row strips; in all
+ * ceil(H / 32) * W * 12 + 4 H + 1280 bytes) lives in
  * a device array of HASF_NOALLOC_SCRATCH_BYTES that the library holds on
  * each device it runs on until the process ends; 4096 x 4096 needs 6 MiB.
  * HASF_EINVAL (nothing enqueued) for the arguments hasf_edt_sq rejects and
@@ -276,6 +278,33 @@ typedef struct {
  * The result of each image equals hasf_filter on that image alone.
  */
 hasf_status hasf_filter_batch(hasf_ctx* ctx, const hasf_image* imgs, int n);
+
+/*
+ * HASF on 3D binary volumes, 26-connected objects and 6-connected background
+ * (Sec. 1: the method smooths 2D and 3D objects; Sec. 4.1: the distance
+ * transforms run on 3D images). A volume is D x H x W contiguous bytes,
+ * voxel (z, y, x) at (z H + y) W + x, nonzero = object; the outside of the box
+ * is background and never changes. For each radius i = 1..r the cutting and
+ * then the filling of Sec. 2 (eq. i, eq. ii) with 3D Euclidean balls; a voxel
+ * is simple iff T26 = 1 and Tbar6 = 1 (26-components of the object voxels of
+ * its 26-neighbourhood; 6-components of the background voxels of its
+ * 18-neighbourhood that contain a face neighbour); thinning and thickening run
+ * levels of increasing squared distance, and in a level rounds of eight
+ * passes over the parity classes (z mod 2, y mod 2, x mod 2) in lexicographic
+ * order until a round changes nothing. C (NULL: empty) is intersected with X.
+ * Limits: D, H, W >= 1, D H W < 2^31, 0 <= r <= HASF_R_MAX. hasf_filter3_batch
+ * filters n volumes in one launch (a workgroup per volume at a time), the
+ * descriptor array being a host array copied before the call returns; the
+ * library allocates 5 D H W bytes of scratch per volume.
+ */
+typedef struct {
+    uint8_t* X;        /* device, in/out */
+    const uint8_t* C;  /* device or NULL */
+    int D, H, W;
+    int r;
+} hasf_volume;
+hasf_status hasf_filter3(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, int D, int H, int W, int r);
+hasf_status hasf_filter3_batch(hasf_ctx* ctx, const hasf_volume* vols, int n);
 
 /*
  * Per-label smoothing of a label (grey-level) image: the binary method of

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_lib", "libhasf.so")
-SOURCES = ["hasf_api.hip", "hasf_filter.hip", "hasf_tile.hip", "hasf_edt.hip", "hasf_topo.hip", "hasf_serve.hip"]
+SOURCES = ["hasf_api.hip", "hasf_filter.hip", "hasf_tile.hip", "hasf_edt.hip", "hasf_topo.hip", "hasf_serve.hip",
+           "hasf_vol.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

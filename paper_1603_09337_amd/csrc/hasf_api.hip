@@ -23,6 +23,7 @@ hipError_t launch_tile(const ImgDesc* d_desc, TileCtl* d_ctl, unsigned* d_err, c
                        hipStream_t stream);
 hipError_t noalloc_init(int device);
 void* noalloc_scratch(int device);
+hipError_t launch_vol(const VolDesc* d_desc, int n, int* d_next, int grid, hipStream_t stream);
 }  // namespace hasf_detail
 
 using namespace hasf_detail;
@@ -816,6 +817,77 @@ hasf_status hasf_filter_cd(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, const ui
 hasf_status hasf_filter_batch(hasf_ctx* ctx, const hasf_image* imgs, int n)
 {
     return run_images(ctx, imgs, n, "hasf_filter_batch");
+}
+
+hasf_status hasf_filter3_batch(hasf_ctx* ctx, const hasf_volume* vols, int n)
+{
+    const char* what = "hasf_filter3_batch";
+    if (!ctx) {
+        set_err(nullptr, "%s: ctx is NULL", what);
+        return HASF_EINVAL;
+    }
+    if (n < 0 || (n > 0 && !vols)) {
+        set_err(ctx, "%s: bad volume array", what);
+        return HASF_EINVAL;
+    }
+    size_t bytes = 0;
+    for (int k = 0; k < n; ++k) {
+        const hasf_volume& v = vols[k];
+        if (!v.X || v.D < 1 || v.H < 1 || v.W < 1 || (long long)v.D * v.H * v.W >= (1ll << 31)) {
+            set_err(ctx, "%s: volume %d: need X != NULL, D, H, W >= 1 and D H W < 2^31", what, k);
+            return HASF_EINVAL;
+        }
+        if (v.r < 0 || v.r > HASF_R_MAX) {
+            set_err(ctx, "%s: volume %d: r = %d outside [0, %d]", what, k, v.r, HASF_R_MAX);
+            return HASF_EINVAL;
+        }
+        bytes += align256(5 * (size_t)v.D * v.H * v.W);
+    }
+    if (n == 0)
+        return HASF_OK;
+    hipSetDevice(ctx->device);
+    const size_t meta = align256(256 + sizeof(VolDesc) * (size_t)n);
+    hasf_status s = ensure_scratch(ctx, meta + bytes);
+    if (s)
+        return s;
+    char* base = (char*)ctx->scratch;
+    char* host = nullptr;
+    if ((s = stage_buffer(ctx, meta, &host)))
+        return s;
+    std::memset(host, 0, meta);  // the queue counter starts at 0
+    VolDesc* d = (VolDesc*)(host + 256);
+    size_t off = meta;
+    for (int k = 0; k < n; ++k) {
+        d[k].X = vols[k].X;
+        d[k].C = vols[k].C;
+        d[k].D = vols[k].D;
+        d[k].H = vols[k].H;
+        d[k].W = vols[k].W;
+        d[k].r = vols[k].r;
+        d[k].work = (uint8_t*)(base + off);
+        off += align256(5 * (size_t)vols[k].D * vols[k].H * vols[k].W);
+    }
+    hipError_t e = hipMemcpyAsync(base, host, meta, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev_stage, ctx->stream);
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "hipMemcpyAsync(volume descriptors)");
+    e = launch_vol((const VolDesc*)(base + 256), n, (int*)base, std::min(n, ctx->num_cu * 2), ctx->stream);
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "hasf_vol_kernel launch");
+    return HASF_OK;
+}
+
+hasf_status hasf_filter3(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, int D, int H, int W, int r)
+{
+    hasf_volume v;
+    v.X = X;
+    v.C = C;
+    v.D = D;
+    v.H = H;
+    v.W = W;
+    v.r = r;
+    return hasf_filter3_batch(ctx, &v, 1);
 }
 
 }  // extern "C"

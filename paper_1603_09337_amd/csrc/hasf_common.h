@@ -156,6 +156,15 @@ struct GridCtl {
     unsigned cnt[HASF_LEVELS_MAX];
 };
 
+// One volume of a 3D batch: the caller's planes and this launch's work planes
+// (S, A, K and two distance planes, D * H * W bytes each).
+struct VolDesc {
+    uint8_t* X;
+    const uint8_t* C;
+    int D, H, W, r;
+    uint8_t* work;
+};
+
 // Control block of one image filtered by row tiles (device memory, zeroed
 // before each launch): the grid barrier, an error word, the last round that
 // changed one of a tile's own rows (1-based over the launch, kept twice by

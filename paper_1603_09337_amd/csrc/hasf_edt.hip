@@ -24,6 +24,17 @@
 //                 costs one saturating add and one min; the result is
 //                 written once. edt_rows is the same with uint16 g, for rows
 //                 too wide for a uint32 strip in LDS.
+//   edt_rows_env  the windowed search costs each pixel about its distance to
+//                 the nearest feature, so a strip with a column whose g
+//                 exceeds ENV_G (or an empty column) is instead listed by
+//                 edt_rows32 and done here, one row per workgroup: the
+//                 minimising column k*(j) of min_k (j - k)^2 + g(k)^2 does
+//                 not decrease with j (the lower envelope of Alg. 2, as
+//                 Meijster's stack traverses it), so k*(j) is found for
+//                 the pixels in bit-reversed order, each one searched only
+//                 between the known k* of its two neighbours at the previous
+//                 level; a level's searches together visit at most W + its
+//                 pixels columns, and long searches are shared by a wave.
 //
 // HBM traffic: 1 B/px read + 4 B/px written, plus 3/8 B/px of masks and
 // carries; the per-column g never leaves LDS. With no feature at all (and no
@@ -45,13 +56,22 @@ constexpr int NO_ROW_BELOW = 0x7FFFFFFF;
 constexpr int CARRY_GROUPS = 16;  // threads per column in edt_colcarry
 constexpr int CARRY_COLS = 16;    // columns per edt_colcarry workgroup
 constexpr int CARRY_REG = 8;      // segments per thread kept in registers by edt_colcarry
+constexpr int ENV_G = 256;        // a strip with a larger column distance (or none) goes to edt_rows_env
+constexpr uint32_t ENV_G2 = (uint32_t)ENV_G * ENV_G;
+constexpr int ENV_BLOCK = 256;    // most threads of an edt_rows_env workgroup (a row per wave)
+constexpr int ENV_SHORT = 48;     // a search over at most this many columns is done by one thread
+constexpr int ENV_W_MAX = 16384;  // widest row edt_rows_env takes (its LDS: 4 bytes per column and wave)
 
 // one thread per 4 columns and 32-row segment: the segment's features as masks
 __global__ __launch_bounds__(256) void edt_colmask(const uint8_t* __restrict__ F, long long ld, int H, int W,
-                                                   int invert, int vec4, uint32_t* __restrict__ mask)
+                                                   int invert, int vec4, uint32_t* __restrict__ mask,
+                                                   int* __restrict__ hard_count)
 {
     const int c4 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
     const int s = blockIdx.y;
+    // the list of strips for edt_rows_env starts empty (this kernel runs first)
+    if (hard_count && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+        *hard_count = 0;
     if (c4 >= W)
         return;
     const int r0 = s * SEG;
@@ -310,12 +330,17 @@ __device__ __forceinline__ uint32_t row_min(const uint32_t* gr, int j, int W, in
 // Workgroups are dealt to the XCDs round-robin; block b takes strip
 // (b % nxcd) * per + b / nxcd, so each XCD takes a contiguous run of strips
 // and the strips of one segment read its masks and carries through one L2.
+//
+// hard_count / hard_list (may be NULL): a strip where some column's g exceeds
+// ENV_G, or has no feature, is appended to hard_list and left to
+// edt_rows_env (its windowed search would cost about g per pixel).
 template <int STRIP>
 __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restrict__ mask,
                                                          const int* __restrict__ above,
                                                          const int* __restrict__ below, int H, int W, int frame,
                                                          int nxcd, int per, uint32_t* __restrict__ d2,
-                                                         long long ldo)
+                                                         long long ldo, int* __restrict__ hard_count,
+                                                         int* __restrict__ hard_list)
 {
     extern __shared__ uint32_t g2s[];
     const int WP = W + 2 * PAD;
@@ -330,7 +355,7 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
         const int r = t / (2 * PAD), k = t - r * (2 * PAD);
         g2s[r * WP + (k < PAD ? k : W + k)] = pad;
     }
-    int has = 0;
+    int has = 0, far = 0;
 #pragma unroll 4
     for (int c = threadIdx.x; c < W; c += blockDim.x) {
         const uint32_t m = mask[(size_t)s * W + c];
@@ -365,7 +390,9 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
             if (frame)
                 g = min(g, min(i + 1, H - i));
             // g < 2^16 whenever it is not "none": a 24-bit multiply is exact
-            g2s[r * WP + PAD + c] = g >= FAR ? G2_INF : __umul24((uint32_t)g, (uint32_t)g);
+            const uint32_t g2 = g >= FAR ? G2_INF : __umul24((uint32_t)g, (uint32_t)g);
+            far |= g2 > ENV_G2;
+            g2s[r * WP + PAD + c] = g2;
         }
     }
     const int any = __syncthreads_or(has);
@@ -373,6 +400,11 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
         for (int r = 0; r < nr; ++r)
             for (int j = threadIdx.x; j < W; j += blockDim.x)
                 d2[(long long)(r0 + r) * ldo + j] = G2_INF;
+        return;
+    }
+    if (__syncthreads_or(far) && hard_list) {
+        if (threadIdx.x == 0)
+            hard_list[atomicAdd(hard_count, 1)] = strip_id;
         return;
     }
 #pragma unroll
@@ -386,6 +418,129 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
     }
 }
 
+// Orders a wave's LDS stores before its lanes' later loads.
+__device__ __forceinline__ void env_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Packed (value, column) for minima that keep the smallest column on ties.
+__device__ __forceinline__ uint64_t env_key(uint32_t f, int k)
+{
+    return ((uint64_t)f << 16) | (uint32_t)k;
+}
+
+__device__ __forceinline__ uint32_t env_f(const uint16_t* g, int j, int k)
+{
+    const uint32_t gk = g[k];
+    const uint32_t g2 = gk == G_INF ? G2_INF : gk * gk;
+    return __builtin_elementwise_add_sat((uint32_t)(j - k) * (uint32_t)(j - k), g2);
+}
+
+// Phase 2 of the rows of the strips that edt_rows32 listed, one row per wave
+// (no workgroup barriers): g of the row from the masks and carries into the
+// wave's LDS (uint16, G_INF for none); then k*(j), the smallest column
+// minimising (j - k)^2 + g(k)^2, for the pixels j = u - 1 in the order of the
+// levels of u = 1..W by decreasing power of two dividing u: k*(j) lies
+// between the k* of u's two neighbours at distance `half`, known from earlier
+// levels (0 and W - 1 beyond the row), since k* never decreases with j. A
+// lane searches its own pixel when the range is short; a long range is
+// searched by the whole wave.
+__global__ __launch_bounds__(ENV_BLOCK) void edt_rows_env(const uint32_t* __restrict__ mask,
+                                                          const int* __restrict__ above,
+                                                          const int* __restrict__ below, int H, int W,
+                                                          int frame, int strip, const int* __restrict__ hard_count,
+                                                          const int* __restrict__ hard_list,
+                                                          uint32_t* __restrict__ d2, long long ldo)
+{
+    extern __shared__ uint32_t env_sm[];
+    const int nwave = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int Wp = (W + 1) & ~1;
+    uint16_t* g = reinterpret_cast<uint16_t*>(env_sm) + (size_t)wave * 2 * Wp;
+    uint16_t* A = g + Wp;  // k*(j)
+    const int nrows = *hard_count * strip;
+    const int L = 32 - __clz((unsigned)W);  // 2^(L-1) <= W < 2^L
+    for (int b = blockIdx.x * nwave + wave; b < nrows; b += gridDim.x * nwave) {
+        const int i = hard_list[b / strip] * strip + b % strip;
+        if (i >= H)
+            continue;  // uniform over the wave: a strip's rows past the image
+        const int s = i / SEG;
+        const int bi = i - s * SEG;
+        for (int c = lane; c < W; c += 64) {
+            const uint32_t m = mask[(size_t)s * W + c];
+            const uint32_t lo = m & (0xFFFFFFFFu >> (31 - bi));  // rows <= i in the segment
+            const uint32_t hi = m >> bi;                         // rows >= i
+            const int up0 = above[(size_t)s * W + c];
+            const int dn0 = below[(size_t)s * W + c];
+            const int up = lo ? s * SEG + 31 - __clz(lo) : up0;
+            const int dn = hi ? i + __ffs(hi) - 1 : dn0;
+            int gv = NO_ROW_BELOW;
+            if (up >= 0)
+                gv = i - up;
+            if (dn != NO_ROW_BELOW)
+                gv = min(gv, dn - i);
+            if (frame)
+                gv = min(gv, min(i + 1, H - i));
+            g[c] = gv == NO_ROW_BELOW ? G_INF : (uint16_t)gv;
+        }
+        env_wave_sync();
+        for (int lev = 0; lev < L; ++lev) {
+            const int half = 1 << (L - 1 - lev);
+            const int step = half << 1;
+            const int npts = (W - half) / step + 1;  // u = half, half + step, ... <= W
+            for (int p0 = 0; p0 < npts; p0 += 64) {
+                const int p = p0 + lane;
+                const bool valid = p < npts;
+                const int u = half + p * step;
+                int lo = 0, hi = W - 1;
+                if (valid) {
+                    lo = u - half >= 1 ? A[u - half - 1] : 0;
+                    hi = u + half <= W ? A[u + half - 1] : W - 1;
+                }
+                const bool lng = valid && hi - lo >= ENV_SHORT;
+                if (valid && !lng) {
+                    uint64_t best = ~0ull;
+                    for (int k = lo; k <= hi; ++k)
+                        best = min(best, env_key(env_f(g, u - 1, k), k));
+                    A[u - 1] = (uint16_t)(best & 0xFFFFu);
+                }
+                uint64_t lm = __ballot(lng);
+                while (lm) {
+                    const int src = __ffsll((long long)lm) - 1;
+                    lm &= lm - 1;
+                    const int j = __shfl(u, src) - 1;
+                    const int klo = __shfl(lo, src), khi = __shfl(hi, src);
+                    uint64_t best = ~0ull;
+                    for (int k = klo + lane; k <= khi; k += 64)
+                        best = min(best, env_key(env_f(g, j, k), k));
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) {
+                        const uint32_t blo = __shfl_xor((uint32_t)best, o);
+                        const uint32_t bhi = __shfl_xor((uint32_t)(best >> 32), o);
+                        best = min(best, ((uint64_t)bhi << 32) | blo);
+                    }
+                    if (lane == 0)
+                        A[j] = (uint16_t)(best & 0xFFFFu);
+                }
+            }
+            env_wave_sync();  // this level's k* before the next level reads them
+        }
+        uint32_t* out = d2 + (long long)i * ldo;
+        for (int j = lane; j < W; j += 64) {
+            uint32_t v = env_f(g, j, A[j]);
+            if (frame) {
+                const uint32_t e = (uint32_t)min(j + 1, W - j);
+                v = min(v, e * e);
+            }
+            out[j] = v;
+        }
+        env_wave_sync();  // the next row rewrites g and A
+    }
+}
+
 }  // namespace
 
 namespace hasf_detail {
@@ -393,7 +548,8 @@ namespace hasf_detail {
 size_t edt_scratch_bytes(int H, int W)
 {
     const size_t nseg = (size_t)(H + SEG - 1) / SEG;
-    return nseg * W * (sizeof(uint32_t) + 2 * sizeof(int)) + 3 * 256;
+    // masks, carries above and below; the count and list of strips for edt_rows_env
+    return nseg * W * (sizeof(uint32_t) + 2 * sizeof(int)) + 3 * 256 + 256 + (size_t)H * sizeof(int) + 256;
 }
 
 // scratch: device memory of edt_scratch_bytes(H, W)
@@ -409,10 +565,16 @@ hipError_t launch_edt(const uint8_t* F, int H, int W, long long ld, int frame, i
     int* above = (int*)p;
     p += ((size_t)nseg * W * sizeof(int) + 255) / 256 * 256;
     int* below = (int*)p;
+    p += ((size_t)nseg * W * sizeof(int) + 255) / 256 * 256;
+    int* hard_count = (int*)p;
+    p += 256;
+    int* hard_list = (int*)p;  // at most one entry per row
+    // rows up to ENV_W_MAX wide that edt_rows32 takes get the envelope for far strips
+    const bool env = W <= ENV_W_MAX;
 
     const int vec4 = ((((uintptr_t)F) | (uintptr_t)ld) & 3) == 0;
     hipLaunchKernelGGL(edt_colmask, dim3((W + 1023) / 1024, nseg), dim3(256), 0, stream, F, ld, H, W, invert, vec4,
-                       mask);
+                       mask, env ? hard_count : nullptr);
     hipLaunchKernelGGL(edt_colcarry, dim3((W + CARRY_COLS - 1) / CARRY_COLS), dim3(CARRY_COLS * CARRY_GROUPS), 0,
                        stream, mask, nseg, W, above, below);
     // strip height: a divisor of 32 (a strip lies in one segment), as LDS
@@ -442,15 +604,31 @@ hipError_t launch_edt(const uint8_t* F, int H, int W, long long ld, int frame, i
         const int nstrips = (H + strip - 1) / strip;
         const int per = (nstrips + nxcd - 1) / nxcd;
         const dim3 grid(per * nxcd);
+        int* hc = env ? hard_count : nullptr;
+        int* hl = env ? hard_list : nullptr;
         if (strip == 4)
             hipLaunchKernelGGL(edt_rows32<4>, grid, dim3(block), 4 * row32, stream, mask, above, below, H, W, frame,
-                               nxcd, per, d2, ldo);
+                               nxcd, per, d2, ldo, hc, hl);
         else if (strip == 2)
             hipLaunchKernelGGL(edt_rows32<2>, grid, dim3(block), 2 * row32, stream, mask, above, below, H, W, frame,
-                               nxcd, per, d2, ldo);
+                               nxcd, per, d2, ldo, hc, hl);
         else
             hipLaunchKernelGGL(edt_rows32<1>, grid, dim3(block), row32, stream, mask, above, below, H, W, frame,
-                               nxcd, per, d2, ldo);
+                               nxcd, per, d2, ldo, hc, hl);
+        if (env) {
+            // the listed strips' rows, a row per wave (nothing when nothing
+            // was listed: each workgroup reads the count and ends)
+            const size_t row_lds = (size_t)((W + 1) & ~1) * 4;
+            const int waves = (int)std::max<size_t>(1, std::min<size_t>(ENV_BLOCK / 64, lds_dyn / 2 / row_lds));
+            static std::atomic<uint64_t> attr_env{0};
+            const hipError_t ee = allow_dyn_lds((const void*)edt_rows_env, (int)lds_dyn, attr_env);
+            if (ee != hipSuccess)
+                return ee;
+            const int rows = nstrips * strip;
+            const int egrid = std::max(1, std::min((rows + waves - 1) / waves, 2048));
+            hipLaunchKernelGGL(edt_rows_env, dim3(egrid), dim3(waves * 64), waves * row_lds, stream, mask, above,
+                               below, H, W, frame, strip, hard_count, hard_list, d2, ldo);
+        }
         return hipGetLastError();
     }
     int strip = 8;

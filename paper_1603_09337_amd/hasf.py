@@ -48,6 +48,11 @@ class _Image(ctypes.Structure):
                 ("order", ctypes.c_int)]
 
 
+class _Volume(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("C", ctypes.c_void_p), ("D", ctypes.c_int), ("H", ctypes.c_int),
+                ("W", ctypes.c_int), ("r", ctypes.c_int)]
+
+
 class _ServeOpts(ctypes.Structure):
     _fields_ = [("pool_bytes", ctypes.c_size_t), ("lanes", ctypes.c_int), ("max_batch", ctypes.c_int),
                 ("max_pending", ctypes.c_int), ("flags", ctypes.c_uint)]
@@ -97,6 +102,8 @@ _lib.hasf_filter.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c
 _lib.hasf_filter_cd.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
                                 ctypes.c_int]
 _lib.hasf_filter_batch.argtypes = [_vp, ctypes.POINTER(_Image), ctypes.c_int]
+_lib.hasf_filter3_batch.argtypes = [_vp, ctypes.POINTER(_Volume), ctypes.c_int]
+_lib.hasf_filter3.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
 _lib.hasf_filter_inf.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
                                  ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.POINTER(ctypes.c_int)]
 _lib.hasf_filter_labels.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
@@ -105,7 +112,7 @@ _lib.hasf_filter_labels.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes
 for _f in ("hasf_create", "hasf_set_stream", "hasf_sync", "hasf_simple_lut", "hasf_edt_sq", "hasf_edt_sq_noalloc",
            "hasf_homotopic_thin", "hasf_homotopic_thicken", "hasf_homotopic_thin_conn",
            "hasf_homotopic_thicken_conn", "hasf_filter", "hasf_filter_cd",
-           "hasf_filter_batch", "hasf_filter_labels", "hasf_filter_inf"):
+           "hasf_filter_batch", "hasf_filter_labels", "hasf_filter_inf", "hasf_filter3", "hasf_filter3_batch"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -288,6 +295,30 @@ class Context:
         self._check(_lib.hasf_filter_inf(self._h, _ptr(X), _ptr(C), _ptr(D), H, W, ld, conn, order, r_max,
                                          HASF_INF_COMPOSED if composed else 0, ctypes.byref(used)))
         return used.value
+
+    @staticmethod
+    def _vol(X, name):
+        if (X is None or X.dtype != torch.uint8 or X.dim() != 3 or not X.is_cuda or not X.is_contiguous()):
+            raise ValueError("%s must be a contiguous 3D uint8 CUDA tensor" % name)
+        return tuple(X.shape)
+
+    def filter3_batch(self, items):
+        """3D HASF, (26,6): items are (X, C or None, r) with X a contiguous
+        (D, H, W) uint8 CUDA tensor, filtered in place in one launch."""
+        arr = (_Volume * max(1, len(items)))()
+        for k, (X, C, r) in enumerate(items):
+            D, H, W = self._vol(X, "X[%d]" % k)
+            if C is not None and (self._vol(C, "C[%d]" % k) != (D, H, W)):
+                raise ValueError("C[%d] must match X's shape" % k)
+            if X.device.index != self.device:
+                raise ValueError("X[%d] is on another device" % k)
+            arr[k] = _Volume(X.data_ptr(), C.data_ptr() if C is not None else None, D, H, W, r)
+        self._stream()
+        self._check(_lib.hasf_filter3_batch(self._h, arr, len(items)))
+        return [it[0] for it in items]
+
+    def filter3(self, X, C=None, r: int = 1):
+        return self.filter3_batch([(X, C, r)])[0]
 
     def plan_batch(self, items):
         """Prepare the descriptor array of a batch once (the tensors must stay alive).

@@ -105,9 +105,17 @@ def test_filter_shapes_workload_and_each_radius():
 
 
 def test_filter_large_image_global_planes():
-    # does not fit in LDS: the planes live in global memory
+    # does not fit in LDS: the planes live in global memory (one workgroup;
+    # by default an image this large goes to row tiles)
+    from paper_1603_09337_amd import hasf
     X, _, _ = synth.workload_disks(H=700, W=1000)
-    say("filter 700x1000 r=3")
+    say("filter 700x1000 r=3, one workgroup, state in global memory")
+    wg = hasf.Context(0, grid_min_pixels=2**64 - 1)
+    d = dev(X)
+    wg.filter(d, None, 3)
+    wg.sync()
+    assert np.array_equal(host(d), oracle.hasf(X, None, 3))
+    say("filter 700x1000 r=3, default")
     assert np.array_equal(_filter_gpu(X, None, 3), oracle.hasf(X, None, 3))
 
 
