@@ -25,16 +25,16 @@
 //                 written once. edt_rows is the same with uint16 g, for rows
 //                 too wide for a uint32 strip in LDS.
 //   edt_rows_env  the windowed search costs each pixel about its distance to
-//                 the nearest feature, so a strip with a column whose g
-//                 exceeds ENV_G (or an empty column) is instead listed by
-//                 edt_rows32 and done here, one row per workgroup: the
-//                 minimising column k*(j) of min_k (j - k)^2 + g(k)^2 does
-//                 not decrease with j (the lower envelope of Alg. 2, as
-//                 Meijster's stack traverses it), so k*(j) is found for
-//                 the pixels in bit-reversed order, each one searched only
-//                 between the known k* of its two neighbours at the previous
-//                 level; a level's searches together visit at most W + its
-//                 pixels columns, and long searches are shared by a wave.
+//                 the nearest feature, so a strip whose column distances
+//                 average more than ENV_AVG is instead listed by edt_rows32
+//                 and done here, one row per workgroup, with Alg. 2's lower
+//                 envelope built in parallel: the lower convex hull of the
+//                 points (k, k^2 + g(k)^2) per band of columns (a stack per
+//                 thread), the bands' hulls merged pairwise in log rounds
+//                 (common lower tangents), then each thread's pixels read
+//                 off the hull by bisection and a forward walk. Its cost
+//                 does not depend on the distances; the frame is applied
+//                 as a minimum at the end, so sparse rows keep small hulls.
 //
 // HBM traffic: 1 B/px read + 4 B/px written, plus 3/8 B/px of masks and
 // carries; the per-column g never leaves LDS. With no feature at all (and no
@@ -56,11 +56,13 @@ constexpr int NO_ROW_BELOW = 0x7FFFFFFF;
 constexpr int CARRY_GROUPS = 16;  // threads per column in edt_colcarry
 constexpr int CARRY_COLS = 16;    // columns per edt_colcarry workgroup
 constexpr int CARRY_REG = 8;      // segments per thread kept in registers by edt_colcarry
-constexpr int ENV_G = 256;        // a strip with a larger column distance (or none) goes to edt_rows_env
-constexpr uint32_t ENV_G2 = (uint32_t)ENV_G * ENV_G;
-constexpr int ENV_BLOCK = 256;    // most threads of an edt_rows_env workgroup (a row per wave)
-constexpr int ENV_SHORT = 48;     // a search over at most this many columns is done by one thread
-constexpr int ENV_W_MAX = 16384;  // widest row edt_rows_env takes (its LDS: 4 bytes per column and wave)
+// A strip goes to edt_rows_env when its pixels' column distances, each
+// counted up to ENV_CAP (a column with no feature counts ENV_CAP), average
+// more than ENV_AVG: the windowed search costs a pixel about its distance.
+constexpr int ENV_AVG = 16;
+constexpr int ENV_CAP = 1024;
+constexpr int ENV_NT = 256;       // threads of an edt_rows_env workgroup (one row at a time)
+constexpr int ENV_W_MAX = 16384;  // widest row edt_rows_env takes (its LDS: about 8 bytes per column)
 
 // one thread per 4 columns and 32-row segment: the segment's features as masks
 __global__ __launch_bounds__(256) void edt_colmask(const uint8_t* __restrict__ F, long long ld, int H, int W,
@@ -331,9 +333,10 @@ __device__ __forceinline__ uint32_t row_min(const uint32_t* gr, int j, int W, in
 // (b % nxcd) * per + b / nxcd, so each XCD takes a contiguous run of strips
 // and the strips of one segment read its masks and carries through one L2.
 //
-// hard_count / hard_list (may be NULL): a strip where some column's g exceeds
-// ENV_G, or has no feature, is appended to hard_list and left to
-// edt_rows_env (its windowed search would cost about g per pixel).
+// hard_count / hard_list (may be NULL): a strip whose column distances
+// average more than ENV_AVG (each counted up to ENV_CAP) is appended to
+// hard_list and left to edt_rows_env (its windowed search would cost about
+// the distance per pixel).
 template <int STRIP>
 __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restrict__ mask,
                                                          const int* __restrict__ above,
@@ -355,7 +358,11 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
         const int r = t / (2 * PAD), k = t - r * (2 * PAD);
         g2s[r * WP + (k < PAD ? k : W + k)] = pad;
     }
-    int has = 0, far = 0;
+    __shared__ uint32_t s_cost;
+    if (threadIdx.x == 0)
+        s_cost = 0;
+    int has = 0;
+    uint32_t cost = 0;
 #pragma unroll 4
     for (int c = threadIdx.x; c < W; c += blockDim.x) {
         const uint32_t m = mask[(size_t)s * W + c];
@@ -391,7 +398,7 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
                 g = min(g, min(i + 1, H - i));
             // g < 2^16 whenever it is not "none": a 24-bit multiply is exact
             const uint32_t g2 = g >= FAR ? G2_INF : __umul24((uint32_t)g, (uint32_t)g);
-            far |= g2 > ENV_G2;
+            cost += (uint32_t)min(g, ENV_CAP);
             g2s[r * WP + PAD + c] = g2;
         }
     }
@@ -402,10 +409,14 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
                 d2[(long long)(r0 + r) * ldo + j] = G2_INF;
         return;
     }
-    if (__syncthreads_or(far) && hard_list) {
-        if (threadIdx.x == 0)
-            hard_list[atomicAdd(hard_count, 1)] = strip_id;
-        return;
+    if (hard_list) {
+        atomicAdd(&s_cost, cost);
+        __syncthreads();
+        if (s_cost > (uint32_t)ENV_AVG * (uint32_t)(nr * W)) {
+            if (threadIdx.x == 0)
+                hard_list[atomicAdd(hard_count, 1)] = strip_id;
+            return;
+        }
     }
 #pragma unroll
     for (int r = 0; r < STRIP; ++r) {
@@ -426,118 +437,310 @@ __device__ __forceinline__ void env_wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Packed (value, column) for minima that keep the smallest column on ties.
-__device__ __forceinline__ uint64_t env_key(uint32_t f, int k)
+// The lower envelope of the parabolas (j - x)^2 + g(x)^2 over the columns x
+// with a feature is the lower convex hull of the points (x, x^2 + g(x)^2):
+// at a pixel j the parabolas' values are j^2 plus a linear function of the
+// point, so the lowest is at a hull vertex, and a column whose point lies on
+// or above the chord of its two hull neighbours is never strictly lowest.
+// Columns are packed with their g as x | g << 16. True when b's point is on
+// or above the chord from a's to c's (xa < xb < xc); |values| < 2^34 and
+// column gaps < 2^14 keep the products exact in 64 bits.
+__device__ __forceinline__ bool env_hidden(uint32_t a, uint32_t b, uint32_t c)
 {
-    return ((uint64_t)f << 16) | (uint32_t)k;
+    const long long xa = a & 0xFFFFu, xb = b & 0xFFFFu, xc = c & 0xFFFFu;
+    const long long ga = a >> 16, gb = b >> 16, gc = c >> 16;
+    const long long ya = xa * xa + ga * ga, yb = xb * xb + gb * gb, yc = xc * xc + gc * gc;
+    return (yb - ya) * (xc - xb) >= (yc - yb) * (xb - xa);
 }
 
-__device__ __forceinline__ uint32_t env_f(const uint16_t* g, int j, int k)
+// (j - x)^2 + g^2 for a packed column; H + W <= 65535 keeps it below 2^32
+__device__ __forceinline__ uint32_t env_f(uint32_t e, int j)
 {
-    const uint32_t gk = g[k];
-    const uint32_t g2 = gk == G_INF ? G2_INF : gk * gk;
-    return __builtin_elementwise_add_sat((uint32_t)(j - k) * (uint32_t)(j - k), g2);
+    const int x = (int)(e & 0xFFFFu);
+    const uint32_t d = (uint32_t)(j > x ? j - x : x - j);
+    const uint32_t g = e >> 16;
+    return d * d + g * g;
 }
 
-// Phase 2 of the rows of the strips that edt_rows32 listed, one row per wave
-// (no workgroup barriers): g of the row from the masks and carries into the
-// wave's LDS (uint16, G_INF for none); then k*(j), the smallest column
-// minimising (j - k)^2 + g(k)^2, for the pixels j = u - 1 in the order of the
-// levels of u = 1..W by decreasing power of two dividing u: k*(j) lies
-// between the k* of u's two neighbours at distance `half`, known from earlier
-// levels (0 and W - 1 beyond the row), since k* never decreases with j. A
-// lane searches its own pixel when the range is short; a long range is
-// searched by the whole wave.
-__global__ __launch_bounds__(ENV_BLOCK) void edt_rows_env(const uint32_t* __restrict__ mask,
-                                                          const int* __restrict__ above,
-                                                          const int* __restrict__ below, int H, int W,
-                                                          int frame, int strip, const int* __restrict__ hard_count,
-                                                          const int* __restrict__ hard_list,
-                                                          uint32_t* __restrict__ d2, long long ldo)
+// Per-row state of edt_rows_env shared by its threads: each thread's band of
+// the packed columns (then its hull, then its pixels' vertices) at
+// E + lane * S, its hull's slice [st, en) of the band, the links of the
+// lanes whose slice is not empty, and per merge group (kept at its first
+// lane) its first and last lane with a non-empty slice.
+struct EnvRow {
+    uint32_t* E;
+    int S;
+    short* st;
+    short* en;
+    short* prv;
+    short* nxt;
+    short* gfirst;
+    short* glast;
+};
+
+// Merges the hulls of the lanes [gl, gl + size) and [gl + size, gl + 2 size)
+// (every column of the left group is left of every column of the right
+// one): the merged hull is a prefix of the left hull and a suffix of the right
+// one, found by removing the left hull's last vertex while it is on or above
+// the chord from its predecessor to the right hull's first vertex, and the
+// right hull's first vertex while it is on or above the chord from the left
+// hull's last vertex to its successor, until neither applies (the common
+// lower tangent). A group's first and last vertices are never removed, so a
+// group's first and last non-empty lanes stay so. Lanes emptied here are
+// unlinked; a link that leaves the group is read as none, so merges of other
+// groups that run at the same time never change a decision here.
+__device__ void env_merge(const EnvRow& r, int gl, int size)
 {
-    extern __shared__ uint32_t env_sm[];
-    const int nwave = blockDim.x >> 6;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int Wp = (W + 1) & ~1;
-    uint16_t* g = reinterpret_cast<uint16_t*>(env_sm) + (size_t)wave * 2 * Wp;
-    uint16_t* A = g + Wp;  // k*(j)
-    const int nrows = *hard_count * strip;
-    const int L = 32 - __clz((unsigned)W);  // 2^(L-1) <= W < 2^L
-    for (int b = blockIdx.x * nwave + wave; b < nrows; b += gridDim.x * nwave) {
-        const int i = hard_list[b / strip] * strip + b % strip;
-        if (i >= H)
-            continue;  // uniform over the wave: a strip's rows past the image
-        const int s = i / SEG;
-        const int bi = i - s * SEG;
-        for (int c = lane; c < W; c += 64) {
-            const uint32_t m = mask[(size_t)s * W + c];
-            const uint32_t lo = m & (0xFFFFFFFFu >> (31 - bi));  // rows <= i in the segment
-            const uint32_t hi = m >> bi;                         // rows >= i
-            const int up0 = above[(size_t)s * W + c];
-            const int dn0 = below[(size_t)s * W + c];
-            const int up = lo ? s * SEG + 31 - __clz(lo) : up0;
-            const int dn = hi ? i + __ffs(hi) - 1 : dn0;
-            int gv = NO_ROW_BELOW;
-            if (up >= 0)
-                gv = i - up;
-            if (dn != NO_ROW_BELOW)
-                gv = min(gv, dn - i);
-            if (frame)
-                gv = min(gv, min(i + 1, H - i));
-            g[c] = gv == NO_ROW_BELOW ? G_INF : (uint16_t)gv;
-        }
-        env_wave_sync();
-        for (int lev = 0; lev < L; ++lev) {
-            const int half = 1 << (L - 1 - lev);
-            const int step = half << 1;
-            const int npts = (W - half) / step + 1;  // u = half, half + step, ... <= W
-            for (int p0 = 0; p0 < npts; p0 += 64) {
-                const int p = p0 + lane;
-                const bool valid = p < npts;
-                const int u = half + p * step;
-                int lo = 0, hi = W - 1;
-                if (valid) {
-                    lo = u - half >= 1 ? A[u - half - 1] : 0;
-                    hi = u + half <= W ? A[u + half - 1] : W - 1;
-                }
-                const bool lng = valid && hi - lo >= ENV_SHORT;
-                if (valid && !lng) {
-                    uint64_t best = ~0ull;
-                    for (int k = lo; k <= hi; ++k)
-                        best = min(best, env_key(env_f(g, u - 1, k), k));
-                    A[u - 1] = (uint16_t)(best & 0xFFFFu);
-                }
-                uint64_t lm = __ballot(lng);
-                while (lm) {
-                    const int src = __ffsll((long long)lm) - 1;
-                    lm &= lm - 1;
-                    const int j = __shfl(u, src) - 1;
-                    const int klo = __shfl(lo, src), khi = __shfl(hi, src);
-                    uint64_t best = ~0ull;
-                    for (int k = klo + lane; k <= khi; k += 64)
-                        best = min(best, env_key(env_f(g, j, k), k));
-#pragma unroll
-                    for (int o = 32; o > 0; o >>= 1) {
-                        const uint32_t blo = __shfl_xor((uint32_t)best, o);
-                        const uint32_t bhi = __shfl_xor((uint32_t)(best >> 32), o);
-                        best = min(best, ((uint64_t)bhi << 32) | blo);
-                    }
-                    if (lane == 0)
-                        A[j] = (uint16_t)(best & 0xFFFFu);
+    const int mid = gl + size, ge = gl + 2 * size;
+    int Lb = r.glast[gl], Rb = r.gfirst[mid];
+    const int first = r.gfirst[gl] >= 0 ? r.gfirst[gl] : r.gfirst[mid];
+    const int last = r.glast[mid] >= 0 ? r.glast[mid] : r.glast[gl];
+    if (Lb >= 0 && Rb >= 0) {
+        for (;;) {
+            const uint32_t* eL = r.E + Lb * r.S;
+            const uint32_t* eR = r.E + Rb * r.S;
+            const uint32_t l1 = eL[r.en[Lb] - 1];
+            uint32_t l0 = 0;
+            bool has_l0 = false;
+            if (r.en[Lb] - 1 > r.st[Lb]) {
+                l0 = eL[r.en[Lb] - 2];
+                has_l0 = true;
+            } else {
+                const int m = r.prv[Lb];
+                if (m >= gl) {
+                    l0 = r.E[m * r.S + r.en[m] - 1];
+                    has_l0 = true;
                 }
             }
-            env_wave_sync();  // this level's k* before the next level reads them
+            const uint32_t r0 = eR[r.st[Rb]];
+            uint32_t r1 = 0;
+            bool has_r1 = false;
+            if (r.st[Rb] + 1 < r.en[Rb]) {
+                r1 = eR[r.st[Rb] + 1];
+                has_r1 = true;
+            } else {
+                const int m = r.nxt[Rb];
+                if (m < ge) {
+                    r1 = r.E[m * r.S + r.st[m]];
+                    has_r1 = true;
+                }
+            }
+            if (has_l0 && env_hidden(l0, l1, r0)) {
+                if (--r.en[Lb] == r.st[Lb]) {
+                    // Lb is emptied: a vertex before it (l0) is in the group
+                    const int p = r.prv[Lb], q = r.nxt[Lb];
+                    r.nxt[p] = (short)q;
+                    r.prv[q] = (short)p;
+                    Lb = p;
+                }
+                continue;
+            }
+            if (has_r1 && env_hidden(l1, r0, r1)) {
+                if (++r.st[Rb] == r.en[Rb]) {
+                    // Rb is emptied: a vertex after it (r1) is in the group
+                    const int p = r.prv[Rb], q = r.nxt[Rb];
+                    if (p >= 0)
+                        r.nxt[p] = (short)q;
+                    r.prv[q] = (short)p;
+                    Rb = q;
+                }
+                continue;
+            }
+            break;
         }
+    }
+    r.gfirst[gl] = (short)first;
+    r.glast[gl] = (short)last;
+}
+
+// Phase 2 of the rows of the strips that edt_rows32 listed: Alg. 2's lower
+// envelope, built in parallel, one row per workgroup of ENV_NT threads,
+// whatever the row's distances:
+//   g of the row from the masks and carries, packed with the column into the
+//   threads' bands of B columns (B the least power of two with B ENV_NT >= W;
+//   a band at a stride of S = B | 1 entries, so neighbouring bands start in
+//   different LDS banks). The frame is left out of g: the distance to the
+//   outside of the window is (i + 1)^2, (H - i)^2, (j + 1)^2 or (W - j)^2,
+//   and the minimum over the features and the outside is the minimum of the
+//   transform without the frame and those four, taken at the end; so a
+//   sparse row keeps few columns with a feature whether or not the frame
+//   counts;
+//   each thread builds the lower hull of its band with a stack, in place (Alg.
+//   2's first scan, on its band);
+//   the hulls are merged pairwise in log2(ENV_NT) rounds (one thread per
+//   pair);
+//   the hull's vertices are gathered in column order (vertex t at t + t / B);
+//   each thread finds the vertex lowest at the first pixel of its band by
+//   bisection (along the hull the values at a fixed pixel fall, then rise)
+//   and walks forward through its band (Alg. 2's second scan), noting each
+//   pixel's vertex in its band;
+//   the row is written from those, coalesced.
+__global__ __launch_bounds__(ENV_NT) void edt_rows_env(const uint32_t* __restrict__ mask,
+                                                       const int* __restrict__ above,
+                                                       const int* __restrict__ below, int H, int W, int frame,
+                                                       int strip, const int* __restrict__ hard_count,
+                                                       const int* __restrict__ hard_list, uint32_t* __restrict__ d2,
+                                                       long long ldo)
+{
+    extern __shared__ uint32_t env_sm[];
+    // (short: with 4 bytes each, four workgroups would not fit a CU at W = 4096)
+    __shared__ short st[ENV_NT], en[ENV_NT], prv[ENV_NT], nxt[ENV_NT], gfirst[ENV_NT], glast[ENV_NT];
+    __shared__ int s_wave[2][ENV_NT / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lb = 31 - __clz((unsigned)((W + ENV_NT - 1) / ENV_NT * 2 - 1));  // B = 2^lb
+    const int B = 1 << lb;
+    const int S = B | 1;
+    const EnvRow r{env_sm, S, st, en, prv, nxt, gfirst, glast};
+    uint32_t* band = env_sm + tid * S;
+    uint32_t* hull = env_sm + ENV_NT * S;
+    const int c0 = min(W, tid * B), nb = min(W, c0 + B) - c0;
+    const int nrows = *hard_count * strip;
+    for (int b = blockIdx.x; b < nrows; b += gridDim.x) {
+        const int i = hard_list[b / strip] * strip + b % strip;
+        if (i >= H)
+            continue;  // uniform: a strip's rows past the image
+        const int s = i / SEG;
+        const int bi = i - s * SEG;
+        const size_t base = (size_t)s * W;
+#pragma unroll 8
+        for (int c = tid; c < W; c += ENV_NT) {
+            const uint32_t m = mask[base + c];
+            const int up0 = above[base + c];
+            const int dn0 = below[base + c];
+            const uint32_t lo = m & (0xFFFFFFFFu >> (31 - bi));  // rows <= i in the segment
+            const uint32_t hi = m >> bi;                         // rows >= i
+            const int up = lo ? s * SEG + 31 - __clz(lo) : up0;
+            const int dn = hi ? i + __ffs(hi) - 1 : dn0;
+            int v = NO_ROW_BELOW;
+            if (up >= 0)
+                v = i - up;
+            if (dn != NO_ROW_BELOW)
+                v = min(v, dn - i);
+            const uint32_t g = v == NO_ROW_BELOW ? G_INF : (uint32_t)v;
+            env_sm[(c >> lb) * S + (c & (B - 1))] = (uint32_t)c | g << 16;
+        }
+        __syncthreads();
+        // the band's hull, a stack over the band's own entries
+        int k = 0;
+        for (int t = 0; t < nb; ++t) {
+            const uint32_t e = band[t];
+            if ((e >> 16) == G_INF)
+                continue;
+            while (k >= 2 && env_hidden(band[k - 2], band[k - 1], e))
+                --k;
+            band[k++] = e;
+        }
+        st[tid] = 0;
+        en[tid] = (short)k;
+        // links of the non-empty lanes: the nearest non-empty lane before and
+        // after each lane (scans over the workgroup), -1 and ENV_NT for none
+        {
+            int lo_v = k ? tid : -1, hi_v = k ? tid : ENV_NT;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int a = __shfl_up(lo_v, o), c = __shfl_down(hi_v, o);
+                if (lane >= o)
+                    lo_v = max(lo_v, a);
+                if (lane + o < 64)
+                    hi_v = min(hi_v, c);
+            }
+            if (lane == 63)
+                s_wave[0][wave] = lo_v;
+            if (lane == 0)
+                s_wave[1][wave] = hi_v;
+            __syncthreads();
+            int carry_lo = -1, carry_hi = ENV_NT;
+#pragma unroll
+            for (int w = 0; w < ENV_NT / 64; ++w) {
+                if (w < wave)
+                    carry_lo = max(carry_lo, s_wave[0][w]);
+                if (w > wave)
+                    carry_hi = min(carry_hi, s_wave[1][w]);
+            }
+            // exclusive: the lanes strictly before and after this one
+            int pe = __shfl_up(lo_v, 1), ne = __shfl_down(hi_v, 1);
+            pe = lane == 0 ? carry_lo : max(pe, carry_lo);
+            ne = lane == 63 ? carry_hi : min(ne, carry_hi);
+            prv[tid] = (short)pe;
+            nxt[tid] = (short)ne;
+            gfirst[tid] = (short)(k ? tid : -1);
+            glast[tid] = (short)(k ? tid : -1);
+        }
+        __syncthreads();
+        for (int size = 1; size < ENV_NT; size <<= 1) {
+            if ((tid & (2 * size - 1)) == 0)
+                env_merge(r, tid, size);
+            __syncthreads();
+        }
+        // gather the hull in column order (an exclusive scan of the slices)
+        const int cnt = en[tid] - st[tid];
+        int pre = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(pre, o);
+            if (lane >= o)
+                pre += v;
+        }
+        if (lane == 63)
+            s_wave[0][wave] = pre;
+        __syncthreads();
+        int n = 0;
+#pragma unroll
+        for (int w = 0; w < ENV_NT / 64; ++w) {
+            pre += w < wave ? s_wave[0][w] : 0;
+            n += s_wave[0][w];
+        }
+        pre -= cnt;
+        for (int t = 0; t < cnt; ++t) {
+            const int h = pre + t;
+            hull[h + (h >> lb)] = band[st[tid] + t];
+        }
+        __syncthreads();  // the bands are free once the hull is gathered
         uint32_t* out = d2 + (long long)i * ldo;
-        for (int j = lane; j < W; j += 64) {
-            uint32_t v = env_f(g, j, A[j]);
+        // the frame's rows above and below (none: G2_INF)
+        const uint32_t fv = frame ? (uint32_t)min(i + 1, H - i) * (uint32_t)min(i + 1, H - i) : G2_INF;
+        if (n == 0) {
+            // no feature in any column: only the frame
+            for (int j = tid; j < W; j += ENV_NT) {
+                const uint32_t e = (uint32_t)min(j + 1, W - j);
+                out[j] = frame ? min(fv, e * e) : G2_INF;
+            }
+            continue;
+        }
+        if (nb > 0) {
+            int lo = 0, hi = n - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                const int m1 = mid + 1;
+                if (env_f(hull[m1 + (m1 >> lb)], c0) <= env_f(hull[mid + (mid >> lb)], c0))
+                    lo = m1;
+                else
+                    hi = mid;
+            }
+            int t = lo;
+            uint32_t cur = hull[t + (t >> lb)];
+            for (int j = 0; j < nb; ++j) {
+                while (t + 1 < n) {
+                    const int t1 = t + 1;
+                    const uint32_t nx = hull[t1 + (t1 >> lb)];
+                    if (env_f(nx, c0 + j) > env_f(cur, c0 + j))
+                        break;
+                    t = t1;
+                    cur = nx;
+                }
+                band[j] = cur;
+            }
+        }
+        __syncthreads();
+        for (int j = tid; j < W; j += ENV_NT) {
+            uint32_t v = env_f(env_sm[(j >> lb) * S + (j & (B - 1))], j);
             if (frame) {
                 const uint32_t e = (uint32_t)min(j + 1, W - j);
-                v = min(v, e * e);
+                v = min(v, min(fv, e * e));
             }
             out[j] = v;
         }
-        env_wave_sync();  // the next row rewrites g and A
+        __syncthreads();  // the next row rewrites the bands and the hull
     }
 }
 
@@ -616,18 +819,23 @@ hipError_t launch_edt(const uint8_t* F, int H, int W, long long ld, int frame, i
             hipLaunchKernelGGL(edt_rows32<1>, grid, dim3(block), row32, stream, mask, above, below, H, W, frame,
                                nxcd, per, d2, ldo, hc, hl);
         if (env) {
-            // the listed strips' rows, a row per wave (nothing when nothing
-            // was listed: each workgroup reads the count and ends)
-            const size_t row_lds = (size_t)((W + 1) & ~1) * 4;
-            const int waves = (int)std::max<size_t>(1, std::min<size_t>(ENV_BLOCK / 64, lds_dyn / 2 / row_lds));
+            // the listed strips' rows, a row per workgroup (nothing when
+            // nothing was listed: each workgroup reads the count and ends);
+            // LDS: the bands (ENV_NT * (B | 1) entries) and the hull (up to
+            // W + W / B entries), uint32 each
+            int B = 1;
+            while (B * ENV_NT < W)
+                B <<= 1;
+            const size_t row_lds = ((size_t)ENV_NT * (B | 1) + W + W / B + 2) * 4;
             static std::atomic<uint64_t> attr_env{0};
-            const hipError_t ee = allow_dyn_lds((const void*)edt_rows_env, (int)lds_dyn, attr_env);
+            // (its static LDS, the lanes' slices and links, is under 4 KiB)
+            const hipError_t ee = allow_dyn_lds((const void*)edt_rows_env, (int)(lds_dyn - 4096), attr_env);
             if (ee != hipSuccess)
                 return ee;
             const int rows = nstrips * strip;
-            const int egrid = std::max(1, std::min((rows + waves - 1) / waves, 2048));
-            hipLaunchKernelGGL(edt_rows_env, dim3(egrid), dim3(waves * 64), waves * row_lds, stream, mask, above,
-                               below, H, W, frame, strip, hard_count, hard_list, d2, ldo);
+            const int egrid = std::max(1, std::min(rows, 2048));
+            hipLaunchKernelGGL(edt_rows_env, dim3(egrid), dim3(ENV_NT), row_lds, stream, mask, above, below, H, W,
+                               frame, strip, hard_count, hard_list, d2, ldo);
         }
         return hipGetLastError();
     }

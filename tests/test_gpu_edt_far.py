@@ -59,6 +59,24 @@ def test_edt_far_edges_and_mixed_strips(frame):
     assert np.array_equal(_edt(T, frame), oracle.edt_sq(T, frame))
 
 
+@pytest.mark.parametrize("frame", [False, True])
+def test_edt_random_low_densities(frame):
+    # every column has features but far apart (long runs of distinct column
+    # distances: large hulls with many vertices removed in the merges), and
+    # the empty image (no feature at all: only the frame, or nothing)
+    for dens, seed in ((0.001, 1), (0.005, 2), (0.02, 3)):
+        F = synth.random_binary(1024, 1500, dens, 300 + seed)
+        say("edt random density", dens, "frame" if frame else "")
+        assert np.array_equal(_edt(F, frame), oracle.edt_sq(F, frame)), dens
+    Z = np.zeros((300, 1100), np.uint8)
+    assert np.array_equal(_edt(Z, frame), oracle.edt_sq(Z, frame))
+    # one feature row in the middle: constant column distances on most rows
+    R = np.zeros((900, 700), np.uint8)
+    R[450, :] = 1
+    R[450, 300:340] = 0
+    assert np.array_equal(_edt(R, frame), oracle.edt_sq(R, frame))
+
+
 def test_edt_sparse_4096_parity_and_timing():
     X, _, _ = synth.workload_large()
     S = _sparse(4096, 4096, 16, 4096)
@@ -81,6 +99,7 @@ def test_edt_sparse_4096_parity_and_timing():
     dense, sparse, sparse_f = t(xd, True), t(sd, False), t(sd, True)
     say("edt 4096^2 ms: dense %.4f, sparse %.4f, sparse with frame %.4f" % (dense, sparse, sparse_f))
     # the far strips take the envelope pass, linear in the row length: a
-    # sparse image costs a bounded multiple of the dense one, not the sum of
-    # its pixels' distances (thousands of times the dense cost)
-    assert sparse < 40 * dense and sparse_f < 40 * dense
+    # sparse image costs a small multiple of the dense one (about 3x on
+    # MI355X), not the sum of its pixels' distances (thousands of times the
+    # dense cost); the bound leaves room for a busy device
+    assert sparse < 6 * dense and sparse_f < 6 * dense
