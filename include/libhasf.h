@@ -362,6 +362,10 @@ typedef struct {
     int max_batch;         /* frames per launch (0 = 1024) */
     int max_pending;       /* submitted but not yet admitted; beyond it submit returns HASF_EAGAIN (0 = 1 << 20) */
     unsigned flags;        /* 0 (HASF_SERVE_PERSISTENT is switched off) */
+    int express_lanes;     /* lanes that take only small frames, so that these never wait for a lane held by a
+                              large frame; with express lanes no launch mixes small and large frames:
+                              -1 = 3/8 of the lanes (at least 1; none with one lane), 0 = none; fewer than lanes */
+    int express_max_pixels;/* a frame of at most this many pixels is small (0 = 1 << 19) */
 } hasf_serve_opts;
 
 typedef struct hasf_server hasf_server;

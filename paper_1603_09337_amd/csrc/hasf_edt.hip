@@ -410,7 +410,11 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
         return;
     }
     if (hard_list) {
-        atomicAdd(&s_cost, cost);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            cost += __shfl_xor(cost, o);
+        if ((threadIdx.x & 63) == 0)
+            atomicAdd(&s_cost, cost);
         __syncthreads();
         if (s_cost > (uint32_t)ENV_AVG * (uint32_t)(nr * W)) {
             if (threadIdx.x == 0)
@@ -833,7 +837,9 @@ hipError_t launch_edt(const uint8_t* F, int H, int W, long long ld, int frame, i
             if (ee != hipSuccess)
                 return ee;
             const int rows = nstrips * strip;
-            const int egrid = std::max(1, std::min(rows, 2048));
+            // four workgroups per CU (the LDS allows four at W = 4096); few
+            // workgroups also keep the launch cheap when nothing was listed
+            const int egrid = std::max(1, std::min(rows, 1024));
             hipLaunchKernelGGL(edt_rows_env, dim3(egrid), dim3(ENV_NT), row_lds, stream, mask, above, below, H, W,
                                frame, strip, hard_count, hard_list, d2, ldo);
         }

@@ -55,7 +55,8 @@ class _Volume(ctypes.Structure):
 
 class _ServeOpts(ctypes.Structure):
     _fields_ = [("pool_bytes", ctypes.c_size_t), ("lanes", ctypes.c_int), ("max_batch", ctypes.c_int),
-                ("max_pending", ctypes.c_int), ("flags", ctypes.c_uint)]
+                ("max_pending", ctypes.c_int), ("flags", ctypes.c_uint), ("express_lanes", ctypes.c_int),
+                ("express_max_pixels", ctypes.c_int)]
 
 
 class _Result(ctypes.Structure):
@@ -370,11 +371,12 @@ class Server:
     tensors filtered in place; keep them alive until wait() returns."""
 
     def __init__(self, ctx: Context, pool_bytes: int = 0, lanes: int = 0, max_batch: int = 0,
-                 max_pending: int = 0, persistent: bool = False):
+                 max_pending: int = 0, persistent: bool = False, express_lanes: int = -1,
+                 express_max_pixels: int = 0):
         self._ctx = ctx
         h = _vp()
         flags = HASF_SERVE_PERSISTENT if persistent else 0
-        opts = _ServeOpts(pool_bytes, lanes, max_batch, max_pending, flags)
+        opts = _ServeOpts(pool_bytes, lanes, max_batch, max_pending, flags, express_lanes, express_max_pixels)
         st = _lib.hasf_serve(ctx._h, ctypes.byref(opts), ctypes.byref(h))
         if st != HASF_OK:
             raise HasfError(st, _lib.hasf_last_error(ctx._h).decode())

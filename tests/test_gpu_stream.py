@@ -212,3 +212,29 @@ def test_grid_frames_in_the_stream():
     assert st["completed"] == 16
     for k, ((X, C, r), g) in enumerate(zip(frames, got)):
         assert np.array_equal(g, oracle.hasf(X, C, r)), "frame %d" % k
+
+
+@pytest.mark.parametrize("express", [0, 1, 3])
+def test_express_lanes_mixed_sizes(express):
+    # small frames (at most 20000 pixels here) go to the express lanes, passing
+    # the large ones; no launch mixes the two classes; every frame exact
+    frames = _frames(24, 40, 260, 71 + express, rmax=7)
+    srv = hasf.Server(ctx(), pool_bytes=256 << 20, lanes=4, express_lanes=express, express_max_pixels=20000)
+    say("stream, %d express lanes, %d small frames" % (express, sum(X.size <= 20000 for X, _, _ in frames)))
+    got, _ = _run(srv, frames, gap_s=0.0002)
+    st = srv.stats()
+    srv.stop()
+    assert st["completed"] == 24
+    for k, ((X, C, r), g) in enumerate(zip(frames, got)):
+        assert np.array_equal(g, oracle.hasf(X, C, r)), "frame %d" % k
+
+
+def test_bad_express_options():
+    for kw in ({"lanes": 4, "express_lanes": 4}, {"lanes": 4, "express_lanes": -2},
+               {"lanes": 2, "express_max_pixels": -1}):
+        with pytest.raises(hasf.HasfError) as e:
+            hasf.Server(ctx(), **kw)
+        assert e.value.status == hasf.HASF_EINVAL, kw
+    # one lane: the default makes no express lane
+    srv = hasf.Server(ctx(), lanes=1)
+    srv.stop()
