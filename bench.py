@@ -175,8 +175,15 @@ def bench_large(ctx, reps=3):
     ms = min(ts)
     ms_avg = sum(ts) / len(ts)
     tiled = ctx.tile_rows >= 0
+    # the library's default tile shape for an image of this size (bands of
+    # 128 rows with 32 halo rows from 8 Mpx on, else 64 and 16; the bands cut
+    # into column tiles of whole 64-column words that fill the CUs)
+    large = X.size >= (1 << 23)
+    th = ctx.tile_rows or (128 if large else 64)
+    halo = ctx.tile_halo or (32 if large else 16)
     out = {"workload": "hasf 4096x4096 r=10, C empty, one image (%s)" %
-           ("row tiles of %d rows in LDS" % (ctx.tile_rows or 32) if tiled else "grid of workgroups"),
+           ("tiles in LDS: bands of %d rows, %d halo rows, cut into column tiles" % (th, halo) if tiled
+            else "grid of workgroups"),
            "ms": round(ms, 2), "ms_avg": round(ms_avg, 2),
            "Mpixel_per_s": round(X.size / ms / 1e3, 2), "frames_per_s": round(1e3 / ms, 3),
            "per_filter": {k: v / counts["launches"] for k, v in counts.items() if k != "launches"}}

@@ -76,11 +76,14 @@ typedef struct {
     size_t batch_grid_min_pixels; /* the same for batches of several images and served frames.
                                      0 = HASF_BATCH_GRID_MIN_PIXELS_DEFAULT; SIZE_MAX = never */
     int tile_rows;          /* large images (hasf_filter, hasf_filter_cd, batches) whose rows fit are filtered
-                               by row tiles of this many own rows, each tile's state in LDS with tile_halo rows
-                               of its neighbours on each side, exchanged every tile_halo / 4 rounds;
-                               0 = HASF_TILE_ROWS_DEFAULT; an even number >= 4 (raised to tile_halo);
+                               by tiles of this many own rows (see tile_cols), each tile's state in LDS with
+                               tile_halo rows of its neighbours above and below, exchanged every tile_halo / 4
+                               rounds;
+                               0 = by image size (HASF_TILE_ROWS_DEFAULT, HASF_TILE_ROWS_LARGE from
+                               HASF_TILE_LARGE_PIXELS on); an even number >= 4 (raised to tile_halo);
                                -1 = never (the grid of workgroups with the state in global memory) */
-    int tile_halo;          /* 0 = HASF_TILE_HALO_DEFAULT; 4, 8, 12 or 16 */
+    int tile_halo;          /* 0 = by image size (HASF_TILE_HALO_DEFAULT, HASF_TILE_HALO_LARGE from
+                               HASF_TILE_LARGE_PIXELS on); a multiple of 4 from 4 to 32 */
     const char* tune_cache; /* NULL: lone images are routed by the fields above. Otherwise the path of a text
                                file of measured launch choices (created if missing, read at hasf_create):
                                the first lone image (hasf_filter, hasf_filter_cd, a batch of one) of a size
@@ -90,10 +93,20 @@ typedef struct {
                                used for that class from then on. Every candidate runs the same schedule, so
                                results do not depend on the choice; the first image of a class costs about
                                2 x (number of candidates) filters more, plus an allocation of H ld bytes. */
+    int tile_cols;          /* each band of tile_rows rows is cut into this many column tiles of whole 64-column
+                               words (each with one word of its neighbours on each side), so that the tiles of an
+                               image fill the CUs; 0 = as many as the CU count allows with at least 8 own words
+                               each; more than the image's words or than the CUs allow is lowered */
 } hasf_opts;
 
-#define HASF_TILE_ROWS_DEFAULT 32
-#define HASF_TILE_HALO_DEFAULT 12
+/* Tile shape by default (measured on MI355X, column tiles filling the CUs):
+ * 2048^2 r=8 8.3 ms with 64 rows and 16 halo rows (32 and 12: 9.8 ms); 4096^2
+ * r=10 28.0 ms with 128 rows and 32 halo rows (64 and 16: 29.5 ms). */
+#define HASF_TILE_ROWS_DEFAULT 64
+#define HASF_TILE_HALO_DEFAULT 16
+#define HASF_TILE_LARGE_PIXELS ((size_t)1 << 23)
+#define HASF_TILE_ROWS_LARGE 128
+#define HASF_TILE_HALO_LARGE 32
 
 /* Create a context on opts->device (opts may be NULL: device 0, defaults).
  * The context owns its scratch memory and the default (null) stream. */

@@ -19,7 +19,7 @@ hipError_t launch_topo(const TopoArgs& a, size_t lds_bytes, hipStream_t stream);
 int filter_occupancy(size_t lds_bytes, int block);
 hipError_t launch_grid(const ImgDesc* d_desc, GridCtl* d_ctl, unsigned* d_err, int grid, hipStream_t stream);
 int grid_occupancy();
-hipError_t launch_tile(const ImgDesc* d_desc, TileCtl* d_ctl, unsigned* d_err, const TilePlan& P,
+hipError_t launch_tile(const ImgDesc* d_desc, TileCtl* d_ctl, unsigned* d_err, const TilePlan& P, int nxcd,
                        hipStream_t stream);
 hipError_t noalloc_init(int device);
 void* noalloc_scratch(int device);
@@ -243,8 +243,12 @@ hasf_status hasf_create(const hasf_opts* opts, hasf_ctx** out)
         set_err(nullptr, "hasf_create: tile_rows must be -1, 0 or an even number >= 4");
         return HASF_EINVAL;
     }
-    if (o.tile_halo != 0 && (o.tile_halo < 4 || o.tile_halo > 16 || (o.tile_halo & 3))) {
-        set_err(nullptr, "hasf_create: tile_halo must be 0, 4, 8, 12 or 16");
+    if (o.tile_halo != 0 && (o.tile_halo < 4 || o.tile_halo > 4 * TILE_ROUNDS_MAX_HOST || (o.tile_halo & 3))) {
+        set_err(nullptr, "hasf_create: tile_halo must be 0 or a multiple of 4 from 4 to 32");
+        return HASF_EINVAL;
+    }
+    if (o.tile_cols < 0) {
+        set_err(nullptr, "hasf_create: tile_cols must be >= 0");
         return HASF_EINVAL;
     }
     int ndev = 0;
@@ -293,7 +297,8 @@ hasf_status hasf_create(const hasf_opts* opts, hasf_ctx** out)
     c->grid_min_px = o.grid_min_pixels ? o.grid_min_pixels : HASF_GRID_MIN_PIXELS_DEFAULT;
     c->batch_grid_min_px = o.batch_grid_min_pixels ? o.batch_grid_min_pixels : HASF_BATCH_GRID_MIN_PIXELS_DEFAULT;
     c->tile_rows = o.tile_rows;
-    c->tile_halo = o.tile_halo ? o.tile_halo : TILE_HALO;
+    c->tile_halo = o.tile_halo;  // 0: by image size
+    c->tile_cols = o.tile_cols;
     if (o.tune_cache && o.tune_cache[0]) {
         c->tune_path = o.tune_cache;
         tune_load(c);
@@ -574,9 +579,10 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
         const hasf_image& im = imgs[big[q]];
         tiles[q].ok = false;
         if (ch.kind == LaunchChoice::TILES)
-            tiles[q] = tile_plan(im.H, im.W, im.r, lds_cap, ctx->num_cu, ch.th, ch.halo);
+            tiles[q] = tile_plan(im.H, im.W, im.r, lds_cap, ctx->num_cu, ch.th, ch.halo, ctx->tile_cols);
         else if (ch.kind < 0 && ctx->tile_rows >= 0)
-            tiles[q] = tile_plan(im.H, im.W, im.r, lds_cap, ctx->num_cu, ctx->tile_rows, ctx->tile_halo);
+            tiles[q] = tile_plan(im.H, im.W, im.r, lds_cap, ctx->num_cu, ctx->tile_rows, ctx->tile_halo,
+                                 ctx->tile_cols);
     }
     size_t bytes = 0, lds_need = 0;
     auto lay_out = [&](ImgDesc& d, const hasf_image& im, size_t cap, const TilePlan* tp) {
@@ -668,7 +674,7 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
         char* m = base + desc_bytes + gmeta * q;
         const ImgDesc* dd = (const ImgDesc*)(m + gmeta - 256);
         if (tiles[q].ok) {
-            e = launch_tile(dd, (TileCtl*)m, ctx->d_grid_err, tiles[q], gs);
+            e = launch_tile(dd, (TileCtl*)m, ctx->d_grid_err, tiles[q], ctx->num_xcd, gs);
             if (e != hipSuccess)
                 return dev_fail(ctx, e, "hasf_tile_kernel launch");
         } else {
@@ -706,7 +712,7 @@ hasf_status run_images(hasf_ctx* ctx, const hasf_image* imgs, int n, const char*
 // measured now. Every candidate filters a copy of the image (same pitch, the
 // image's C and D) twice; the second run is timed with events on the
 // context's stream. Candidates: one workgroup (up to 4 Mpx), row tiles of
-// 16 to 48 rows with 8 or 12 halo rows (those whose band fits LDS), and the
+// 32 to 128 rows with 12 to 32 halo rows (those whose band fits LDS), and the
 // grid kernel.
 hasf_status tune_choice(hasf_ctx* ctx, const hasf_image& im, const char* what, LaunchChoice* out)
 {
@@ -720,9 +726,9 @@ hasf_status tune_choice(hasf_ctx* ctx, const hasf_image& im, const char* what, L
     if ((size_t)im.H * im.W <= ((size_t)1 << 22))
         cand.push_back(LaunchChoice{LaunchChoice::WORKGROUP, 0, 0, 0.f});
     const size_t lds_cap = std::min(ctx->lds_per_block, (size_t)160 * 1024) - 2048;
-    const int tries[][2] = {{16, 8}, {24, 12}, {32, 8}, {32, 12}, {48, 12}};
+    const int tries[][2] = {{32, 12}, {64, 16}, {64, 24}, {128, 24}, {128, 32}};
     for (const auto& t : tries) {
-        const TilePlan P = tile_plan(im.H, im.W, im.r, lds_cap, ctx->num_cu, t[0], t[1]);
+        const TilePlan P = tile_plan(im.H, im.W, im.r, lds_cap, ctx->num_cu, t[0], t[1], ctx->tile_cols);
         bool dup = false;
         for (const auto& c : cand)
             dup |= c.kind == LaunchChoice::TILES && c.th == P.TH && c.halo == P.halo;

@@ -178,23 +178,44 @@ struct TileCtl {
     unsigned lev[4 * HASF_R_MAX][HASF_LEVELS_MAX];
 };
 
-// Row tiles: halo rows kept on each side of a tile (by default; 4, 8, 12 or
-// 16), so that a tile runs halo / 4 rounds between two exchanges (a pass
-// moves information by one row, a round is four passes).
-constexpr int TILE_HALO = HASF_TILE_HALO_DEFAULT;
 constexpr int TILE_NT = 1024;  // threads of a tile's workgroup
 
-// Tiling of one image: tiles of TH own rows (TH even, >= halo), the last one
-// shorter; each keeps up to ER = TH + 2 halo rows in LDS.
+// Tiling of one image: nr row bands of TH own rows (TH even, >= halo), the
+// last one shorter, each cut into nc column tiles of about WW / nc own words
+// (64 columns each); a tile keeps up to ER = TH + 2 halo rows and WWb = its
+// own words + TILE_HALO_WORDS on each side in LDS. Tile t is row band t / nc,
+// column tile t % nc.
 struct TilePlan {
     bool ok;
     int TH, ntiles, ER, halo;
+    int nr, nc, WWb;
     size_t lds_bytes;     // dynamic LDS of a tile
     size_t planes_bytes;  // Rg, A, K, Dp (row-major), two exchange copies (sub-images)
-    size_t ent_words;     // level entry slots per tile: levels(r) x ER x WW
+    size_t ent_words;     // level entry slots per tile: levels(r) x ER x WWb
     size_t idx_bytes, msk_bytes;
     size_t total() const { return planes_bytes + idx_bytes + msk_bytes; }
 };
+
+// Halo words (of 64 columns) a column tile keeps on each side: at least the
+// passes run between two exchanges (4 x TILE_ROUNDS_MAX_HOST <= 64 columns).
+constexpr int TILE_HALO_WORDS = 1;
+
+// Own words [tile_cw0(c), tile_cw0(c + 1)) of column tile c of nc, WW words
+// in a row (the same split on the host and on the device)
+__host__ __device__ inline int tile_cw0(int c, int nc, int WW)
+{
+    return (int)(((long long)c * WW) / nc);
+}
+
+// Band words of the widest column tile
+__host__ __device__ inline int tile_band_words(int nc, int WW)
+{
+    if (nc <= 1)
+        return WW;
+    const int own = (WW + nc - 1) / nc;
+    const int b = own + 2 * TILE_HALO_WORDS;
+    return b < WW ? b : WW;
+}
 
 __host__ __device__ inline size_t tile_sub_words(int H, int W)  // one exchange copy: 4 sub-images of 32-bit words
 {
@@ -253,52 +274,76 @@ inline ImageLayout image_layout(int H, int W, int r, size_t lds_cap)
 }
 
 // Most rounds a tile runs between two exchanges (also in hasf_device.h).
-constexpr int TILE_ROUNDS_MAX_HOST = 4;
+constexpr int TILE_ROUNDS_MAX_HOST = 8;
+static_assert(4 * TILE_ROUNDS_MAX_HOST <= 64 * TILE_HALO_WORDS, "a column tile's halo covers the passes between exchanges");
 
-// Own rows per tile when the caller does not choose.
-constexpr int TILE_ROWS_DEFAULT = HASF_TILE_ROWS_DEFAULT;
 
-// Tiling of an H x W image at radius r with tiles of TH_req own rows (0: the
-// default), at most max_tiles tiles (taller tiles when needed). Not ok when a
-// band of `halo` own rows and its halos does not fit lds_cap bytes of LDS
-// (very wide images), or when the image would be one tile.
-inline TilePlan tile_plan(int H, int W, int r, size_t lds_cap, int max_tiles, int TH_req, int halo = TILE_HALO)
+// Tiling of an H x W image at radius r with row bands of TH_req own rows and
+// `halo` halo rows (0: the defaults by image size), at most max_tiles tiles in
+// all (taller bands when needed),
+// each band cut into NC_req column tiles (0: as many as max_tiles allows, at
+// least 8 own words each, so that the tiles fill the CUs). Not ok when a band
+// of `halo` own rows and its halos does not fit lds_cap bytes of LDS, or when
+// the image would be one tile.
+inline TilePlan tile_plan(int H, int W, int r, size_t lds_cap, int max_tiles, int TH_req, int halo = 0,
+                          int NC_req = 0)
 {
     TilePlan P{};
     P.ok = false;
-    if (halo < 4 || halo > 4 * TILE_ROUNDS_MAX_HOST || (halo & 3))
+    // the default shape by image size
+    const bool large = (size_t)H * (size_t)W >= HASF_TILE_LARGE_PIXELS;
+    if (halo == 0)
+        halo = large ? HASF_TILE_HALO_LARGE : HASF_TILE_HALO_DEFAULT;
+    if (TH_req == 0)
+        TH_req = large ? HASF_TILE_ROWS_LARGE : HASF_TILE_ROWS_DEFAULT;
+    if (halo < 4 || halo > 4 * TILE_ROUNDS_MAX_HOST || (halo & 3) || max_tiles < 2)
         return P;
     P.halo = halo;
-    const size_t WW = (size_t)(W + 63) / 64, NWD = (size_t)H * WW;
-    int ercap = 0;
-    while (ercap < H + 2 * halo && hasf_align256(state_bytes(ercap + 2, W, true)) <= lds_cap)
-        ercap += 2;
-    const int thmax = ((ercap - 2 * halo) / 2) * 2;
-    if (thmax < halo || max_tiles < 2)
-        return P;
-    int th = TH_req > 0 ? TH_req : TILE_ROWS_DEFAULT;
+    const int WW = (W + 63) / 64;
+    const size_t NWD = (size_t)H * WW;
+    int th = TH_req;
     th = th < halo ? halo : th;
     th = (th + 1) / 2 * 2;
-    th = th > thmax ? thmax : th;
-    if ((H + th - 1) / th > max_tiles) {
+    int nr = (H + th - 1) / th;
+    if (nr > max_tiles) {
         th = (H + max_tiles - 1) / max_tiles;
         th = (th + 1) / 2 * 2;
-        if (th > thmax)
+        nr = (H + th - 1) / th;
+    }
+    int ncap = max_tiles / nr;
+    ncap = ncap < WW ? ncap : WW;
+    int nc = NC_req > 0 ? NC_req : WW / 8;
+    nc = nc < ncap ? nc : ncap;
+    nc = nc < 1 ? 1 : nc;
+    const int WWb = tile_band_words(nc, WW);
+    const int Wb = nc > 1 ? 64 * WWb : W;  // band width in columns
+    int ercap = 0;
+    while (ercap < H + 2 * halo && hasf_align256(state_bytes(ercap + 2, Wb, true)) <= lds_cap)
+        ercap += 2;
+    const int thmax = ((ercap - 2 * halo) / 2) * 2;
+    if (thmax < halo)
+        return P;
+    if (th > thmax) {
+        th = thmax;
+        nr = (H + th - 1) / th;
+        if (nr * nc > max_tiles)
             return P;
     }
-    const int nt = (H + th - 1) / th;
-    if (nt < 2)
+    if (nr * nc < 2)
         return P;
     P.ok = true;
     P.TH = th;
-    P.ntiles = nt;
+    P.nr = nr;
+    P.nc = nc;
+    P.WWb = WWb;
+    P.ntiles = nr * nc;
     P.ER = th + 2 * halo < H ? th + 2 * halo : H;
-    P.lds_bytes = hasf_align256(state_bytes(P.ER, W, true));
+    P.lds_bytes = hasf_align256(state_bytes(P.ER, Wb, true));
     P.planes_bytes = hasf_align256(4 * NWD * 8) + 2 * hasf_align256(tile_sub_words(H, W) * 4);
     const size_t nlev = (size_t)(r > 0 ? hasf_levels(r) : 1);
-    P.ent_words = nlev * (size_t)P.ER * WW;
-    P.idx_bytes = hasf_align256((size_t)nt * P.ent_words * 4);
-    P.msk_bytes = hasf_align256((size_t)nt * P.ent_words * 8);
+    P.ent_words = nlev * (size_t)P.ER * (size_t)WWb;
+    P.idx_bytes = hasf_align256((size_t)P.ntiles * P.ent_words * 4);
+    P.msk_bytes = hasf_align256((size_t)P.ntiles * P.ent_words * 8);
     return P;
 }
 
@@ -352,8 +397,9 @@ struct hasf_ctx {
     // workgroups: alone (hasf_filter, a batch of one), in batches and served
     size_t grid_min_px, batch_grid_min_px;
     // own rows per tile of the row-tile path for large images (0: default;
-    // -1: large images always go to the grid kernel) and halo rows per side
-    int tile_rows, tile_halo;
+    // -1: large images always go to the grid kernel), halo rows per side and
+    // column tiles per row band (0: as many as fill the CUs)
+    int tile_rows, tile_halo, tile_cols;
     // measured launch choices of lone images by size class, and the file they
     // are kept in (empty: no tuning)
     std::map<uint64_t, LaunchChoice> tune;

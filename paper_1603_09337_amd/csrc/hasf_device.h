@@ -123,6 +123,47 @@ __device__ __forceinline__ uint32_t expand4(uint32_t nib)
     return (nib * 0x00204081u) & 0x01010101u;
 }
 
+// One 64-bit word of the nonzero bytes p[0 .. n) (n <= 64; 16-byte loads
+// when vec and n == 64, p then being 16-byte aligned).
+__device__ __forceinline__ uint64_t pack_word(const uint8_t* __restrict__ p, int n, bool vec)
+{
+    uint64_t m = 0;
+    if (vec && n == 64) {
+        const uint4* xp = reinterpret_cast<const uint4*>(p);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            uint4 v = xp[j];
+            uint64_t bits = nz4(v.x) | (nz4(v.y) << 4) | (nz4(v.z) << 8) | (nz4(v.w) << 12);
+            m |= bits << (16 * j);
+        }
+    } else {
+        for (int j = 0; j < n; ++j)
+            m |= (uint64_t)(p[j] != 0) << j;
+    }
+    return m;
+}
+
+// Bits 0 .. n - 1 of m as bytes 0/1 at p (the same alignment rule).
+__device__ __forceinline__ void unpack_word(uint8_t* __restrict__ p, int n, uint64_t m, bool vec)
+{
+    if (vec && n == 64) {
+        uint4* xp = reinterpret_cast<uint4*>(p);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t b16 = (uint32_t)(m >> (16 * j)) & 0xFFFFu;
+            uint4 v;
+            v.x = expand4(b16 & 0xF);
+            v.y = expand4((b16 >> 4) & 0xF);
+            v.z = expand4((b16 >> 8) & 0xF);
+            v.w = expand4((b16 >> 12) & 0xF);
+            xp[j] = v;
+        }
+    } else {
+        for (int j = 0; j < n; ++j)
+            p[j] = (uint8_t)((m >> j) & 1u);
+    }
+}
+
 // Row-major 64-bit words of the nonzero bytes of X (and of C n X into K when
 // K is given): one thread per word. Threads t0, t0 + tn, ... of the caller's
 // range (a workgroup, or every workgroup of a grid) share the words.
@@ -136,37 +177,11 @@ __device__ void pack_rows(const uint8_t* __restrict__ X, const uint8_t* __restri
         const int row = q / WW;
         const int w = q - row * WW;
         const int c0 = w * 64;
-        const uint8_t* xr = X + (long long)row * ld + c0;
-        const uint8_t* cr = C ? C + (long long)row * ld + c0 : nullptr;
-        uint64_t m = 0, k = 0;
-        if (vec_ok && c0 + 64 <= W) {
-            const uint4* xp = reinterpret_cast<const uint4*>(xr);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                uint4 v = xp[j];
-                uint64_t bits = nz4(v.x) | (nz4(v.y) << 4) | (nz4(v.z) << 8) | (nz4(v.w) << 12);
-                m |= bits << (16 * j);
-            }
-            if (cr) {
-                const uint4* cp = reinterpret_cast<const uint4*>(cr);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    uint4 v = cp[j];
-                    uint64_t bits = nz4(v.x) | (nz4(v.y) << 4) | (nz4(v.z) << 8) | (nz4(v.w) << 12);
-                    k |= bits << (16 * j);
-                }
-            }
-        } else {
-            const int n = min(64, W - c0);
-            for (int j = 0; j < n; ++j) {
-                m |= (uint64_t)(xr[j] != 0) << j;
-                if (cr)
-                    k |= (uint64_t)(cr[j] != 0) << j;
-            }
-        }
+        const int n = min(64, W - c0);
+        const uint64_t m = pack_word(X + (long long)row * ld + c0, n, vec_ok);
         R[q] = m;
         if (K)
-            K[q] = k & m;
+            K[q] = (C ? pack_word(C + (long long)row * ld + c0, n, vec_ok) : 0ull) & m;
     }
 }
 
@@ -191,25 +206,7 @@ __device__ void unpack_rows(uint8_t* __restrict__ X, long long ld, int H, int W,
         const int row = q / WW;
         const int w = q - row * WW;
         const int c0 = w * 64;
-        uint8_t* xr = X + (long long)row * ld + c0;
-        const uint64_t m = R[q];
-        if (vec_ok && c0 + 64 <= W) {
-            uint4* xp = reinterpret_cast<uint4*>(xr);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t b16 = (uint32_t)(m >> (16 * j)) & 0xFFFFu;
-                uint4 v;
-                v.x = expand4(b16 & 0xF);
-                v.y = expand4((b16 >> 4) & 0xF);
-                v.z = expand4((b16 >> 8) & 0xF);
-                v.w = expand4((b16 >> 12) & 0xF);
-                xp[j] = v;
-            }
-        } else {
-            const int n = min(64, W - c0);
-            for (int j = 0; j < n; ++j)
-                xr[j] = (uint8_t)((m >> j) & 1u);
-        }
+        unpack_word(X + (long long)row * ld + c0, min(64, W - c0), R[q], vec_ok);
     }
 }
 
@@ -276,8 +273,8 @@ __device__ void clear_candidates(const Img<LDS>& g, int t0, int tn)
 // changed something.
 // TILE rounds (see run_rounds) flag a change of the tile's own rows in round
 // k at CTL_TCHG + k.
-enum { CTL_CHG = 0, CTL_CNT = 2, CTL_PROD = 4, CTL_WORDS = 8, CTL_PROD2 = 8, CTL_TCHG = 12, CTL_LDS_WORDS = 16 };
-constexpr int TILE_ROUNDS_MAX = 4;
+enum { CTL_CHG = 0, CTL_CNT = 2, CTL_PROD = 4, CTL_WORDS = 8, CTL_PROD2 = 8, CTL_TCHG = 12, CTL_LDS_WORDS = 20 };
+constexpr int TILE_ROUNDS_MAX = 8;
 static_assert(TILE_ROUNDS_MAX == TILE_ROUNDS_MAX_HOST, "rounds between tile exchanges");
 
 // per-phase scheduling state (uniform registers)
@@ -523,15 +520,16 @@ __device__ __forceinline__ bool test_word(const PassPtrs<LDS>& p, int idx, int r
 // the workgroup barrier between listing and testing.
 // NT: the workgroup size (threads) the caller is launched with.
 //
-// TILE: the state is one tile of a larger image (its own rows plus halo rows
-// whose values a neighbouring tile owns). Exactly `nrounds` (at most
-// TILE_ROUNDS_MAX) rounds run, since the caller decides when the level ends
-// over all tiles, and the result is the number k of rounds run until the
-// last one that changed one of the tile's own rows [ilo, ihi) (0: none did).
+// TILE: the state is one tile of a larger image (its own pixels plus halo
+// rows and words whose values a neighbouring tile owns). Exactly `nrounds`
+// (at most TILE_ROUNDS_MAX) rounds run, since the caller decides when the
+// level ends over all tiles, and the result is the number k of rounds run
+// until the last one that changed one of the tile's own pixels (rows
+// [ilo, ihi), words [wlo, whi)) (0: none did).
 // Otherwise the result is 0.
 template <bool LDS, int NT = BLOCK, bool TILE = false>
 __device__ __forceinline__ int run_rounds(const Img<LDS>& g, bool thin, Sched& sc, int nrounds = 0, int ilo = 0,
-                                          int ihi = 0)
+                                          int ihi = 0, int wlo = 0, int whi = 0)
 {
     const int WW = g.WW;
     const float invWW = 1.0f / (float)WW;
@@ -586,13 +584,15 @@ __device__ __forceinline__ int run_rounds(const Img<LDS>& g, bool thin, Sched& s
             const int nw = rows * WW;
             const PassPtrs<LDS> pp = pass_ptrs(g, si, sj);
             bool changed_here = false;
-            bool changed_own = false;  // TILE: a change in rows [ilo, ihi)
+            bool changed_own = false;  // TILE: a change in rows [ilo, ihi), words [wlo, whi)
             auto test = [&](int idx) {
                 const int rr = row_of(idx);
                 const bool c = test_word(pp, idx, rr, si, sj, WW, g.H, flip, g.conn4);
                 changed_here |= c;
-                if constexpr (TILE)
-                    changed_own |= c && 2 * rr + si >= ilo && 2 * rr + si < ihi;
+                if constexpr (TILE) {
+                    const int w = idx - rr * WW;
+                    changed_own |= c && 2 * rr + si >= ilo && 2 * rr + si < ihi && w >= wlo && w < whi;
+                }
             };
             if (nw <= 2 * NT) {
                 // one chunk of 128 words per wave, listed at L[w0 ..] and

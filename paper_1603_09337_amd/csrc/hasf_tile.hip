@@ -1,18 +1,20 @@
-// One large image filtered by row tiles whose state stays in LDS (the
-// schedule of thinning H and thickening *H of Sec. 2, run with temporal
-// blocking).
+// One large image filtered by tiles whose state stays in LDS (the schedule
+// of thinning H and thickening *H of Sec. 2, run with temporal blocking).
 //
-// Tile t (one workgroup) owns image rows [t TH, (t + 1) TH) and also keeps
-// `halo` rows on each side that its neighbours own, so its LDS state is a
-// band of up to TH + 2 halo rows in the layout of the per-image kernel. A
-// subfield pass decides a pixel from its 3x3 neighbourhood, so after k passes
-// a band's rows can differ from the whole-image schedule only within k rows
-// of the band's cut edges: a tile runs halo / 4 rounds (4 passes each, halo
-// passes in all) on its own and its own rows are then exactly the
-// schedule's. Then every tile publishes its first and last halo own rows,
-// the tiles meet at one grid barrier, and each replaces
-// its halo rows with its neighbours' (flagging every word whose test reads
-// a changed word). A level of the schedule ends after the first round that
+// The image is cut into row bands of TH rows, and each band into column
+// tiles of whole 64-column words. Tile t (one workgroup) owns rows [r0, r1)
+// and words [cw0, cw1) of its band and also keeps `halo` rows above and below
+// and TILE_HALO_WORDS words left and right that its neighbours own, so its
+// LDS state is a block of up to TH + 2 halo rows in the layout of the
+// per-image kernel. A subfield pass decides a pixel from its 3x3
+// neighbourhood, so after k passes a block can differ from the whole-image
+// schedule only within k rows or columns of its cut edges: a tile runs
+// halo / 4 rounds (4 passes each, halo passes in all, at most 16 < 64
+// columns) on its own and its own pixels are then exactly the schedule's.
+// Then every tile publishes its own pixels that its neighbours keep (its
+// first and last halo rows, its first and last halo words), the tiles meet at
+// one grid barrier, and each replaces its halo with its neighbours' pixels
+// (flagging every word whose test reads a changed word). A level of the schedule ends after the first round that
 // changes nothing anywhere; the tiles learn it at the barrier that follows,
 // and the rounds they ran after it changed nothing. So the result is the
 // schedule's bit for bit, with one grid barrier per halo / 4 rounds instead
@@ -24,6 +26,7 @@
 // rows alike. The saved set A, the constraint K and the background
 // constraint Dp are row-major planes in global memory, written by the owners
 // of the rows and read by the stages.
+#include <algorithm>
 #include <atomic>
 
 #include "hasf_device.h"
@@ -94,7 +97,8 @@ struct TileView {
     size_t slots;
     int H, WW;
     uint64_t lastmask;
-    int e0, ER, r0, r1;  // band rows [e0, e0 + ER); own rows [r0, r1)
+    int e0, ER, r0, r1;  // block rows [e0, e0 + ER); own rows [r0, r1)
+    int bw0, WWb, cw0, cw1;  // block words [bw0, bw0 + WWb); own words [cw0, cw1)
     bool hasK, hasD;
 };
 
@@ -138,19 +142,20 @@ __device__ __attribute__((noinline)) void tile_stage(const TileView& v, int mode
 {
     constexpr BallPairs P = make_ball_pairs(I);
     const bool frame = (mode == HC_THIN || mode == HF_THIN);
-    const int nwb = v.ER * v.WW;
+    const int nwb = v.ER * v.WWb;
     const int nq = (nwb + TILE_NT - 1) / TILE_NT * TILE_NT;
     for (int q = threadIdx.x; q < nq; q += TILE_NT) {
         uint64_t base = 0;
-        int lrow = 0, w = 0, row = 0;
+        int lrow = 0, wb = 0, w = 0, row = 0;
         if (q < nwb) {
-            lrow = q / v.WW;
-            w = q - lrow * v.WW;
+            lrow = q / v.WWb;
+            wb = q - lrow * v.WWb;
+            w = v.bw0 + wb;  // image word
             row = v.e0 + lrow;
             const size_t gq = (size_t)row * v.WW + w;
             const uint64_t s = v.Rg[gq];
             const uint64_t valid = (w == v.WW - 1) ? v.lastmask : ~0ull;
-            const bool own = row >= v.r0 && row < v.r1;
+            const bool own = row >= v.r0 && row < v.r1 && w >= v.cw0 && w < v.cw1;
             switch (mode) {
             case HC_THIN:
                 base = s & ~(v.hasK ? v.K[gq] : 0ull);
@@ -208,7 +213,7 @@ __device__ __attribute__((noinline)) void tile_stage(const TileView& v, int mode
             acc |= x & ~cov & base;
             cov |= x;
             if (k == P.n - 1 || P.v[k + 1] != P.v[k]) {
-                tile_flush(v, cnt, P.rank[k], lrow, w, acc);
+                tile_flush(v, cnt, P.rank[k], lrow, wb, acc);
                 acc = 0;
             }
         }
@@ -250,54 +255,69 @@ __device__ int tile_levels_at(int i)
 // The whole band's geometry and planes.
 struct Band {
     Img<true> g;
-    int t, nt, r0, r1, e0, ER, lo, hi;  // lo, hi: own rows in band coordinates
+    int tr, nr, tc, nc;                 // row band and column tile, and their counts
+    int r0, r1, e0, ER, lo, hi;         // lo, hi: own rows in block coordinates
+    int cw0, cw1, bw0, WWg;             // own words, first block word, words of an image row
     int halo;
     size_t SUBG;                        // words per sub-image of an exchange copy
     glb_u32* Xs[2];
 };
 
-// Own rows [r0, r0 + halo) and [r1 - halo, r1) (the rows the neighbours
-// keep as halo) into exchange copy `out`.
+// The own pixels the neighbours keep as halo, into exchange copy `out`
+// (image coordinates): own rows [r0, r0 + halo) and [r1 - halo, r1) over the
+// own words, and the own words [cw0, cw0 + hw) and [cw1 - hw, cw1) over the
+// own rows (hw = TILE_HALO_WORDS; only towards existing neighbours).
 __device__ __forceinline__ void publish(const Band& b, glb_u32* out)
 {
     const Img<true>& g = b.g;
-    const int WW = g.WW;
-    const int top_hi = b.t > 0 ? min(b.r1, b.r0 + b.halo) : b.r0;
-    const int bot_lo = b.t < b.nt - 1 ? max(top_hi, b.r1 - b.halo) : b.r1;
+    const int WWb = g.WW, nw = b.cw1 - b.cw0;
+    const int top_hi = b.tr > 0 ? min(b.r1, b.r0 + b.halo) : b.r0;
+    const int bot_lo = b.tr < b.nr - 1 ? max(top_hi, b.r1 - b.halo) : b.r1;
     const int ntop = top_hi - b.r0;
-    const int n = (ntop + (b.r1 - bot_lo)) * 2 * WW;
-    for (int u = threadIdx.x; u < n; u += TILE_NT) {
-        const int hr = u / (2 * WW);
-        const int rem = u - hr * 2 * WW;
-        const int sj = rem >= WW ? 1 : 0;
-        const int w = rem - sj * WW;
-        const int y = hr < ntop ? b.r0 + hr : bot_lo + (hr - ntop);
+    auto put = [&](int y, int gw, int sj) {
         const int si = y & 1;
-        out[(size_t)(si * 2 + sj) * b.SUBG + (size_t)(y >> 1) * WW + w] =
-            g.S[g.sub(si, sj) + ((y - b.e0) >> 1) * WW + w];
+        out[(size_t)(si * 2 + sj) * b.SUBG + (size_t)(y >> 1) * b.WWg + gw] =
+            g.S[g.sub(si, sj) + ((y - b.e0) >> 1) * WWb + (gw - b.bw0)];
+    };
+    const int n = (ntop + (b.r1 - bot_lo)) * 2 * nw;
+    for (int u = threadIdx.x; u < n; u += TILE_NT) {
+        const int hr = u / (2 * nw);
+        const int rem = u - hr * 2 * nw;
+        const int sj = rem >= nw ? 1 : 0;
+        const int w = rem - sj * nw;
+        put(hr < ntop ? b.r0 + hr : bot_lo + (hr - ntop), b.cw0 + w, sj);
+    }
+    // edge words of the own rows (the rows above are published twice when
+    // they are also in the first and last halo rows: the same value)
+    const int hl = b.tc > 0 ? min(TILE_HALO_WORDS, nw) : 0;
+    const int hrr = b.tc < b.nc - 1 ? min(TILE_HALO_WORDS, nw) : 0;
+    const int ne = hl + hrr;
+    if (ne == 0)
+        return;
+    const int m = (b.r1 - b.r0) * 2 * ne;
+    for (int u = threadIdx.x; u < m; u += TILE_NT) {
+        const int y = b.r0 + u / (2 * ne);
+        const int rem = u % (2 * ne);
+        const int sj = rem >= ne ? 1 : 0;
+        const int k = rem - sj * ne;
+        put(y, k < hl ? b.cw0 + k : b.cw1 - hrr + (k - hl), sj);
     }
 }
 
-// Halo rows [e0, r0) and [r1, e1) from exchange copy `in` (the neighbours'
-// own rows). A changed word is written and every word whose test reads it
-// (the 3 x 3 word block around it in each sub-image) is flagged; *s_flag
-// records that something changed.
+// The halo from exchange copy `in` (the neighbours' own pixels): rows
+// [e0, r0) and [r1, e1) over all block words, and the halo words left and
+// right of the own words over the own rows. A changed word is written and
+// every word whose test reads it (the 3 x 3 word block around it in each
+// sub-image) is flagged; *s_flag records that something changed.
 __device__ __forceinline__ void refresh_halo(const Band& b, const glb_u32* in, int* s_flag)
 {
     const Img<true>& g = b.g;
-    const int WW = g.WW;
-    const int ntop = b.r0 - b.e0, nbot = b.e0 + b.ER - b.r1;
-    const int n = (ntop + nbot) * 2 * WW;
-    for (int u = threadIdx.x; u < n; u += TILE_NT) {
-        const int hr = u / (2 * WW);
-        const int rem = u - hr * 2 * WW;
-        const int sj = rem >= WW ? 1 : 0;
-        const int w = rem - sj * WW;
-        const int y = hr < ntop ? b.e0 + hr : b.r1 + (hr - ntop);
+    const int WWb = g.WW;
+    auto get = [&](int y, int wb, int sj) {
         const int si = y & 1;
-        const uint32_t nv = in[(size_t)(si * 2 + sj) * b.SUBG + (size_t)(y >> 1) * WW + w];
+        const uint32_t nv = in[(size_t)(si * 2 + sj) * b.SUBG + (size_t)(y >> 1) * b.WWg + (b.bw0 + wb)];
         const int rr = (y - b.e0) >> 1;
-        const int li = g.sub(si, sj) + rr * WW + w;
+        const int li = g.sub(si, sj) + rr * WWb + wb;
         if (g.S[li] != nv) {
             g.S[li] = nv;
 #pragma unroll
@@ -310,16 +330,36 @@ __device__ __forceinline__ void refresh_halo(const Band& b, const glb_u32* in, i
                         continue;
 #pragma unroll
                     for (int dc = -1; dc <= 1; ++dc) {
-                        const int ww = w + dc;
-                        if (ww < 0 || ww >= WW)
+                        const int ww = wb + dc;
+                        if (ww < 0 || ww >= WWb)
                             continue;
-                        g.D[g.sub(a, 0) + x * WW + ww] = 1;
-                        g.D[g.sub(a, 1) + x * WW + ww] = 1;
+                        g.D[g.sub(a, 0) + x * WWb + ww] = 1;
+                        g.D[g.sub(a, 1) + x * WWb + ww] = 1;
                     }
                 }
             }
             *s_flag = 1;
         }
+    };
+    const int ntop = b.r0 - b.e0, nbot = b.e0 + b.ER - b.r1;
+    const int n = (ntop + nbot) * 2 * WWb;
+    for (int u = threadIdx.x; u < n; u += TILE_NT) {
+        const int hr = u / (2 * WWb);
+        const int rem = u - hr * 2 * WWb;
+        const int sj = rem >= WWb ? 1 : 0;
+        get(hr < ntop ? b.e0 + hr : b.r1 + (hr - ntop), rem - sj * WWb, sj);
+    }
+    const int hl = b.cw0 - b.bw0, hrr = b.bw0 + WWb - b.cw1;
+    const int ne = hl + hrr;
+    if (ne == 0)
+        return;
+    const int m = (b.r1 - b.r0) * 2 * ne;
+    for (int u = threadIdx.x; u < m; u += TILE_NT) {
+        const int y = b.r0 + u / (2 * ne);
+        const int rem = u % (2 * ne);
+        const int sj = rem >= ne ? 1 : 0;
+        const int k = rem - sj * ne;
+        get(y, k < hl ? k : (b.cw1 - b.bw0) + (k - hl), sj);
     }
 }
 
@@ -348,7 +388,8 @@ __device__ __forceinline__ bool tile_levels(Band& b, const TileView& v, TileSync
         unsigned lvl_last = start;  // the level's last round that changed something
         for (;;) {
             const int epoch_rounds = b.halo >> 2;
-            const int last = run_rounds<true, TILE_NT, true>(g, thin, sc, epoch_rounds, b.lo, b.hi);
+            const int last = run_rounds<true, TILE_NT, true>(g, thin, sc, epoch_rounds, b.lo, b.hi, b.cw0 - b.bw0,
+                                                             b.cw1 - b.bw0);
             publish(b, b.Xs[ts.gen & 1]);
             // by barrier parity: a tile that reads this epoch's word after
             // the barrier never sees a store of the next epoch (a faster
@@ -389,23 +430,37 @@ __device__ __forceinline__ bool tile_levels(Band& b, const TileView& v, TileSync
 }
 
 __device__ __forceinline__ bool tile_image(const ImgDesc* __restrict__ dp, TileSync& ts, int* s_ok, int* s_flag,
-                                           uint64_t* smem, lds_u32* cnt, lds_i32* ctl, int TH, int ERmax, int halo)
+                                           uint64_t* smem, lds_u32* cnt, lds_i32* ctl, int TH, int ERmax, int halo,
+                                           int nc, int WWbmax, int nxcd)
 {
     const int H = dp->H, W = dp->W;
+    const int WW = (W + 63) >> 6;
     Band b;
     b.halo = halo;
-    b.t = blockIdx.x;
-    b.nt = gridDim.x;
-    b.r0 = b.t * TH;
+    // tiles of one XCD form a run (workgroups are dealt to the XCDs round
+    // robin), so most halo exchanges stay within one L2
+    const int nx = nxcd > 1 && gridDim.x % nxcd == 0 ? nxcd : 1;
+    const int t = (int)(blockIdx.x % nx) * (int)(gridDim.x / nx) + (int)(blockIdx.x / nx);
+    b.nc = nc;
+    b.nr = (int)gridDim.x / nc;
+    b.tr = t / nc;
+    b.tc = t - b.tr * nc;
+    b.r0 = b.tr * TH;
     b.r1 = min(H, b.r0 + TH);
     b.e0 = max(0, b.r0 - halo);
     b.ER = min(H, b.r1 + halo) - b.e0;
     b.lo = b.r0 - b.e0;
     b.hi = b.r1 - b.e0;
+    b.WWg = WW;
+    b.cw0 = tile_cw0(b.tc, nc, WW);
+    b.cw1 = tile_cw0(b.tc + 1, nc, WW);
+    b.bw0 = nc > 1 ? max(0, b.cw0 - TILE_HALO_WORDS) : 0;
+    const int bw1 = nc > 1 ? min(WW, b.cw1 + TILE_HALO_WORDS) : WW;
     Img<true>& g = b.g;
     g.ctl = ctl;
     g.H = b.ER;
-    g.W = W;
+    // the block's columns: whole words, up to the image's last column
+    g.W = min(W, 64 * bw1) - 64 * b.bw0;
     bind_state(g, (void*)smem);
     g.A = g.K = g.Dp = nullptr;
     g.eidx = nullptr;
@@ -413,7 +468,7 @@ __device__ __forceinline__ bool tile_image(const ImgDesc* __restrict__ dp, TileS
     g.hasK = dp->C != nullptr;
     g.hasD = dp->D != nullptr;
     g.conn4 = dp->conn4 != 0;
-    const int WW = g.WW;
+    const int WWb = g.WW;  // bw1 - bw0
     const size_t NWD = (size_t)H * WW;
     glb_u64* Rg = (glb_u64*)dp->gplanes;
     glb_u64* A = Rg + NWD;
@@ -430,31 +485,48 @@ __device__ __forceinline__ bool tile_image(const ImgDesc* __restrict__ dp, TileS
     v.A = A;
     v.K = K;
     v.Dp = Dp;
-    v.slots = (size_t)ERmax * WW;
-    v.eidx = (glb_u32*)dp->ent_idx + (size_t)b.t * nlev_max * v.slots;
-    v.emsk = (glb_u64*)dp->ent_msk + (size_t)b.t * nlev_max * v.slots;
+    v.slots = (size_t)ERmax * WWbmax;
+    v.eidx = (glb_u32*)dp->ent_idx + (size_t)t * nlev_max * v.slots;
+    v.emsk = (glb_u64*)dp->ent_msk + (size_t)t * nlev_max * v.slots;
     v.H = H;
     v.WW = WW;
-    v.lastmask = g.lastmask;
+    v.lastmask = (W & 63) ? ((1ull << (W & 63)) - 1ull) : ~0ull;
     v.e0 = b.e0;
     v.ER = b.ER;
     v.r0 = b.r0;
     v.r1 = b.r1;
+    v.bw0 = b.bw0;
+    v.WWb = WWb;
+    v.cw0 = b.cw0;
+    v.cw1 = b.cw1;
     v.hasK = g.hasK;
     v.hasD = g.hasD;
     const int tid = threadIdx.x;
     const long long ld = dp->ld;
+    const int nown = b.cw1 - b.cw0;
+    const int own_lo = b.cw0 - b.bw0;  // first own word in the block
 
-    // own rows packed into the global planes, then the band into LDS
-    pack_rows(dp->X + (long long)b.r0 * ld, dp->C ? dp->C + (long long)b.r0 * ld : nullptr, ld, b.r1 - b.r0, W,
-              Rg + (size_t)b.r0 * WW, g.hasK ? K + (size_t)b.r0 * WW : nullptr, tid, TILE_NT);
-    if (g.hasD)
-        pack_background(dp->D + (long long)b.r0 * ld, ld, b.r1 - b.r0, W, Rg + (size_t)b.r0 * WW,
-                        Dp + (size_t)b.r0 * WW, tid, TILE_NT);
+    // own pixels packed into the global planes, then the block into LDS
+    const bool vec_ok = ((((uintptr_t)dp->X) | (dp->C ? (uintptr_t)dp->C : 0) |
+                          (dp->D ? (uintptr_t)dp->D : 0) | (uintptr_t)ld) & 15) == 0;
+    for (int q = tid; q < (b.r1 - b.r0) * nown; q += TILE_NT) {
+        const int row = b.r0 + q / nown;
+        const int w = b.cw0 + q % nown;
+        const int n = min(64, W - 64 * w);
+        const size_t gq = (size_t)row * WW + w;
+        const uint64_t m = pack_word(dp->X + (long long)row * ld + 64 * w, n, vec_ok);
+        Rg[gq] = m;
+        if (g.hasK)
+            K[gq] = pack_word(dp->C + (long long)row * ld + 64 * w, n, vec_ok) & m;
+        if (g.hasD)
+            Dp[gq] = pack_word(dp->D + (long long)row * ld + 64 * w, n, vec_ok) & ~m;
+    }
     if (!tile_sync(ts, s_ok))
         return false;
-    for (int q = tid; q < b.ER * WW; q += TILE_NT)
-        g.R[q] = Rg[(size_t)b.e0 * WW + q];
+    for (int q = tid; q < b.ER * WWb; q += TILE_NT) {
+        const int lr = q / WWb;
+        g.R[q] = Rg[(size_t)(b.e0 + lr) * WW + b.bw0 + (q - lr * WWb)];
+    }
     __syncthreads();
     rows_to_sub(g, tid, TILE_NT);
     __syncthreads();
@@ -466,12 +538,12 @@ __device__ __forceinline__ bool tile_image(const ImgDesc* __restrict__ dp, TileS
         for (int k = 0; k < 4; ++k, ++pi) {
             const int ph = (k + rot) & 3;
             if (pi > 0) {
-                // own rows of the set into the row-major copy the stages read
-                for (int q = b.lo * WW + tid; q < b.hi * WW; q += TILE_NT) {
-                    const int lr = q / WW;
-                    const int w = q - lr * WW;
-                    const int o = (lr >> 1) * WW + w;
-                    Rg[(size_t)b.e0 * WW + q] =
+                // own pixels of the set into the row-major copy the stages read
+                for (int q = tid; q < (b.hi - b.lo) * nown; q += TILE_NT) {
+                    const int lr = b.lo + q / nown;
+                    const int wb = own_lo + q % nown;
+                    const int o = (lr >> 1) * WWb + wb;
+                    Rg[(size_t)(b.e0 + lr) * WW + b.bw0 + wb] =
                         spread_bits(g.S[g.sub(lr & 1, 0) + o]) | (spread_bits(g.S[g.sub(lr & 1, 1) + o]) << 1);
                 }
                 if (!tile_sync(ts, s_ok))
@@ -492,21 +564,29 @@ __device__ __forceinline__ bool tile_image(const ImgDesc* __restrict__ dp, TileS
                 return false;
         }
     }
-    // the own rows of the result
+    // the own pixels of the result
     sub_to_rows(g, tid, TILE_NT);
     __syncthreads();
-    unpack_rows(dp->X + (long long)b.r0 * ld, ld, b.r1 - b.r0, W, g.R + (size_t)b.lo * WW, tid, TILE_NT);
+    for (int q = tid; q < (b.r1 - b.r0) * nown; q += TILE_NT) {
+        const int lr = b.lo + q / nown;
+        const int wb = own_lo + q % nown;
+        const int w = b.bw0 + wb;
+        unpack_word(dp->X + (long long)(b.e0 + lr) * ld + 64 * w, min(64, W - 64 * w), g.R[lr * WWb + wb],
+                    vec_ok);
+    }
     return true;
 }
 
 }  // namespace
 
-// One image over gridDim.x row tiles of TH own rows and `halo` halo rows
-// (ERmax: the longest band, which sizes the entry lists). If a grid barrier
+// One image over gridDim.x tiles: nc column tiles per band of TH own rows,
+// `halo` halo rows (ERmax rows and WWbmax words: the largest block, which
+// sizes the entry lists). If a grid barrier
 // gave up, tc->err and the caller's sticky word are set (the image is then
 // undefined).
 __global__ __launch_bounds__(TILE_NT) void hasf_tile_kernel(const ImgDesc* __restrict__ dp, TileCtl* tc,
-                                                            unsigned* err_out, int TH, int ERmax, int halo)
+                                                            unsigned* err_out, int TH, int ERmax, int halo, int nc,
+                                                            int WWbmax, int nxcd)
 {
     extern __shared__ uint64_t smem[];
     __shared__ unsigned cnt[HASF_LEVELS_MAX];
@@ -515,7 +595,8 @@ __global__ __launch_bounds__(TILE_NT) void hasf_tile_kernel(const ImgDesc* __res
     if (threadIdx.x == 0)
         s_flag = 0;
     TileSync ts{tc, gridDim.x, 0u, 0u, 0u, 0u};
-    const bool ok = tile_image(dp, ts, &s_ok, &s_flag, smem, (lds_u32*)cnt, (lds_i32*)ctl, TH, ERmax, halo);
+    const bool ok =
+        tile_image(dp, ts, &s_ok, &s_flag, smem, (lds_u32*)cnt, (lds_i32*)ctl, TH, ERmax, halo, nc, WWbmax, nxcd);
     if (!ok && threadIdx.x == 0) {
         __hip_atomic_store(&tc->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (err_out)
@@ -532,15 +613,19 @@ __global__ __launch_bounds__(TILE_NT) void hasf_tile_kernel(const ImgDesc* __res
 
 namespace hasf_detail {
 
-hipError_t launch_tile(const ImgDesc* d_desc, TileCtl* d_ctl, unsigned* d_err, const TilePlan& P,
+hipError_t launch_tile(const ImgDesc* d_desc, TileCtl* d_ctl, unsigned* d_err, const TilePlan& P, int nxcd,
                        hipStream_t stream)
 {
     static std::atomic<uint64_t> attr{0};
     const hipError_t e = allow_dyn_lds((const void*)hasf_tile_kernel, 160 * 1024 - 2048, attr);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(hasf_tile_kernel, dim3(P.ntiles), dim3(TILE_NT), P.lds_bytes, stream, d_desc, d_ctl, d_err,
-                       P.TH, P.ER, P.halo);
+    // more than half a CU's LDS: one tile per CU (at most one tile per CU
+    // is planned), so that the dispatcher cannot put two tiles on one CU
+    // while others stay idle
+    const size_t lds = std::max(P.lds_bytes, (size_t)(80 * 1024 + 256));
+    hipLaunchKernelGGL(hasf_tile_kernel, dim3(P.ntiles), dim3(TILE_NT), lds, stream, d_desc, d_ctl, d_err, P.TH,
+                       P.ER, P.halo, P.nc, P.WWb, nxcd);
     return hipGetLastError();
 }
 

@@ -39,7 +39,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 class _Opts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("hbm_budget", ctypes.c_size_t), ("flags", ctypes.c_uint),
                 ("grid_min_pixels", ctypes.c_size_t), ("batch_grid_min_pixels", ctypes.c_size_t),
-                ("tile_rows", ctypes.c_int), ("tile_halo", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
+                ("tile_rows", ctypes.c_int), ("tile_halo", ctypes.c_int), ("tune_cache", ctypes.c_char_p),
+                ("tile_cols", ctypes.c_int)]
 
 
 class _Image(ctypes.Structure):
@@ -186,7 +187,7 @@ def _companion(T, X, name):
 class Context:
     def __init__(self, device: int = 0, hbm_budget: int = 0, grid_min_pixels: int = 0,
                  batch_grid_min_pixels: int = 0, tile_rows: int = 0, tile_halo: int = 0,
-                 tune_cache: str = None):
+                 tune_cache: str = None, tile_cols: int = 0):
         import torch
         self._torch = torch
         self.device = device
@@ -194,7 +195,7 @@ class Context:
         self.tile_halo = tile_halo
         h = _vp()
         opts = _Opts(device, hbm_budget, 0, grid_min_pixels, batch_grid_min_pixels, tile_rows, tile_halo,
-                     tune_cache.encode() if tune_cache else None)
+                     tune_cache.encode() if tune_cache else None, tile_cols)
         st = _lib.hasf_create(ctypes.byref(opts), ctypes.byref(h))
         if st != HASF_OK:
             raise HasfError(st, _lib.hasf_last_error(None).decode())

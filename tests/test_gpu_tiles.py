@@ -23,7 +23,7 @@ _CTX = {}
 def tctx(th):
     """Every image on the large-image path: row tiles of th rows (-1: the grid kernel)."""
     if th not in _CTX:
-        _CTX[th] = hasf.Context(0, grid_min_pixels=1, batch_grid_min_pixels=1, tile_rows=th)
+        _CTX[th] = hasf.Context(0, grid_min_pixels=1, batch_grid_min_pixels=1, tile_rows=th, tile_halo=12)
     return _CTX[th]
 
 
@@ -140,7 +140,7 @@ def test_bad_tile_rows_is_refused():
 _HCTX = {}
 
 
-@pytest.mark.parametrize("halo", [4, 12, 16])
+@pytest.mark.parametrize("halo", [4, 12, 16, 24, 32])
 def test_tiles_other_halo_depths(halo):
     # halo / 4 rounds between exchanges; tiles at least as tall as the halo
     if halo not in _HCTX:
@@ -155,6 +155,81 @@ def test_tiles_other_halo_depths(halo):
     X, C, r = synth.workload_shapes()
     say("tiles, halo", halo, "512x512 r=5")
     assert np.array_equal(_filter(c, X, C, r), oracle.hasf(X, C, r))
-    for bad in (2, 6, 20):
+    for bad in (2, 6, 30, 36):
         with pytest.raises(hasf.HasfError):
             hasf.Context(0, tile_halo=bad)
+    # the same with column tiles (one word of halo covers up to 32 passes)
+    key = ("cols", halo)
+    if key not in _HCTX:
+        _HCTX[key] = hasf.Context(0, grid_min_pixels=1, batch_grid_min_pixels=1, tile_rows=8, tile_halo=halo,
+                                  tile_cols=3)
+    X = synth.random_binary(150, 500, 0.5, 824)
+    say("column tiles, halo", halo)
+    assert np.array_equal(_filter(_HCTX[key], X, None, 5), oracle.hasf(X, None, 5))
+
+
+_CTX2 = {}
+
+
+def t2ctx(th, nc):
+    """Every image on the large-image path: bands of th rows cut into nc column tiles."""
+    if (th, nc) not in _CTX2:
+        _CTX2[(th, nc)] = hasf.Context(0, grid_min_pixels=1, batch_grid_min_pixels=1, tile_rows=th, tile_halo=12,
+                                       tile_cols=nc)
+    return _CTX2[(th, nc)]
+
+
+TILE2D_CASES = [
+    # (H, W, r, density, with C, tile rows, column tiles, seed): column tiles of
+    # whole 64-column words, one word of halo on each side
+    (40, 200, 2, 0.6, False, 8, 2, 1),     # 4 words: column tiles of 2 words
+    (37, 130, 3, 0.55, True, 8, 3, 2),     # 3 words, 3 tiles of one word each; last row band short
+    (100, 300, 4, 0.45, True, 10, 5, 3),   # 5 words, one per tile
+    (129, 700, 6, 0.5, False, 24, 4, 4),   # ragged last word (700 = 10 * 64 + 60)
+    (64, 1000, 8, 0.5, True, 16, 3, 5),
+    (300, 520, 3, 0.5, False, 8, 2, 6),    # 38 bands x 2
+    (18, 1500, 2, 0.5, False, 8, 7, 7),
+    (61, 400, 12, 0.5, True, 8, 2, 8),     # radius beyond the halo
+    (20, 4000, 3, 0.5, False, 12, 16, 9),  # one band of 20 rows, 16 column tiles
+]
+
+
+@pytest.mark.parametrize("case", TILE2D_CASES)
+def test_column_tiles_random(case):
+    H, W, r, dens, withC, th, nc, seed = case
+    X = synth.random_binary(H, W, dens, 800 + seed)
+    C = synth.random_binary(H, W, 0.05, 850 + seed) if withC else None
+    say("column tiles", case)
+    assert np.array_equal(_filter(t2ctx(th, nc), X, C, r), oracle.hasf(X, C, r))
+
+
+@pytest.mark.parametrize("n", [8, 4])
+def test_column_tiles_cd_order_pitch(n):
+    X = synth.disks_image(90, 450, np.random.default_rng(31))
+    rng = np.random.default_rng(32)
+    C = ((rng.random(X.shape) < 0.03) & (X != 0)).astype(np.uint8)
+    D = ((rng.random(X.shape) < 0.05) & (X == 0)).astype(np.uint8)
+    for order in (0, 1):
+        say("column tiles C, D, conn", n, "order", order)
+        exp = oracle.hasf(X, C, 4, D=D, n=n, order=order)
+        assert np.array_equal(_filter(t2ctx(12, 3), X, C, 4, pitch=467, D=D, n=n, order=order), exp)
+
+
+def test_column_tiles_same_schedule_counts():
+    # the same rounds and levels as one band per row tile and as the grid kernel
+    X, _, _ = synth.workload_disks(H=300, W=1000)
+    outs, counts = [], []
+    for c in (t2ctx(16, 1), t2ctx(16, 4), tctx(-1)):
+        c.grid_counts(reset=True)
+        outs.append(_filter(c, X, None, 5))
+        counts.append(c.grid_counts(reset=True))
+    assert np.array_equal(outs[0], oracle.hasf(X, None, 5))
+    assert all(np.array_equal(o, outs[0]) for o in outs[1:])
+    assert counts[0]["rounds"] == counts[1]["rounds"] == counts[2]["rounds"]
+    assert counts[0]["levels"] == counts[1]["levels"] == counts[2]["levels"]
+
+
+def test_bad_tile_cols_is_refused():
+    with pytest.raises(hasf.HasfError) as e:
+        hasf.Context(0, tile_cols=-1)
+    assert e.value.status == hasf.HASF_EINVAL

@@ -20,11 +20,11 @@ BIG = 2**64 - 1
 # every candidate of the tuner, as context options
 CHOICES = {
     "workgroup": dict(grid_min_pixels=BIG, batch_grid_min_pixels=BIG),
-    "tiles16/8": dict(grid_min_pixels=1, tile_rows=16, tile_halo=8),
-    "tiles24/12": dict(grid_min_pixels=1, tile_rows=24, tile_halo=12),
-    "tiles32/8": dict(grid_min_pixels=1, tile_rows=32, tile_halo=8),
     "tiles32/12": dict(grid_min_pixels=1, tile_rows=32, tile_halo=12),
-    "tiles48/12": dict(grid_min_pixels=1, tile_rows=48, tile_halo=12),
+    "tiles64/16": dict(grid_min_pixels=1, tile_rows=64, tile_halo=16),
+    "tiles64/24": dict(grid_min_pixels=1, tile_rows=64, tile_halo=24),
+    "tiles128/24": dict(grid_min_pixels=1, tile_rows=128, tile_halo=24),
+    "tiles128/32": dict(grid_min_pixels=1, tile_rows=128, tile_halo=32),
     "grid": dict(grid_min_pixels=1, tile_rows=-1),
 }
 _CTX = {}
