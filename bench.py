@@ -75,9 +75,31 @@ ROUND_BYTES_PER_PX = 1.375
 # HBM bytes per hasf_edt_sq call on the 4096x4096 input, from rocprofv3 --pmc
 # (FETCH_SIZE, WRITE_SIZE of the EDT kernels of the same calls as bench_edt)
 EDT_COUNTS = os.path.join(ROOT, "profiles", "edt_4096_counters.json")
-# HBM bytes of one whole 4096x4096 r=10 filter on the grid path, from the same
-# rocprofv3 --pmc runs
+# HBM bytes of one whole 4096x4096 r=10 filter (the tile kernel), from the
+# same rocprofv3 --pmc runs
 LARGE_COUNTS = os.path.join(ROOT, "profiles", "filter_4096x4096_r10_counters.json")
+
+
+def sources_sha256():
+    """SHA-256 over the kernel sources (paper_1603_09337_amd/csrc, sorted by
+    name): the counter files record the value they were taken at, and their
+    figures are used only while it still matches."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1603_09337_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def load_counts(path):
+    """A counter file's figures, or None when it is missing or was taken on
+    other kernel sources."""
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    return d if d.get("sources_sha256") == sources_sha256() else None
 
 
 def parse():
@@ -139,9 +161,8 @@ def bench_edt(ctx, reps=20):
     t = e0.elapsed_time(e1) / 1e3 / reps
     bytes_ = EDT_BYTES_PER_PX * Hn * Wn
     bytes_l = EDT_BYTES_PER_PX_LAYOUT * Hn * Wn
-    traffic = None
-    if os.path.exists(EDT_COUNTS):
-        traffic = json.load(open(EDT_COUNTS)).get("hbm_bytes_per_call")
+    ec = load_counts(EDT_COUNTS)
+    traffic = ec.get("hbm_bytes_per_call") if ec else None
     return {"bound": "hbm", "achieved": round(bytes_ / t / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": round(bytes_ / t / HBM_PEAK, 4), "traffic": traffic, "us_per_call": round(t * 1e6, 1),
             "workload": "hasf_edt_sq 4096x4096, border is feature (the 4096x4096 r=10 input)",
@@ -193,10 +214,9 @@ def bench_large(ctx, reps=3):
     rounds = counts["rounds"] / counts["launches"]
     alg = ROUND_BYTES_PER_PX * X.size * rounds
     traffic = None
-    if os.path.exists(LARGE_COUNTS):
-        lc = json.load(open(LARGE_COUNTS))
-        if lc.get("kernel") == ("hasf_tile_kernel" if tiled else "hasf_grid_kernel"):
-            traffic = lc.get("hbm_bytes_per_filter")
+    lc = load_counts(LARGE_COUNTS)
+    if lc and lc.get("kernel") == ("hasf_tile_kernel" if tiled else "hasf_grid_kernel"):
+        traffic = lc.get("hbm_bytes_per_filter")
     out["roofline"] = {"bound": "hbm", "achieved": round(alg / (ms_avg / 1e3) / 1e9, 1), "peak": HBM_PEAK / 1e9,
                        "unit": "GB/s", "frac": round(alg / (ms_avg / 1e3) / HBM_PEAK, 4), "traffic": traffic,
                        "kernel": "hasf_tile_kernel" if tiled else "hasf_grid_kernel",
@@ -538,9 +558,7 @@ def main():
     batch_diag = {"kernel": "hasf_filter_kernel<512>", "kernel_ms": round(kern_s * 1e3, 3),
                   "compulsory_bytes": 3 * H * W * B,
                   "compulsory_GB_per_s": round(3 * H * W * B / kern_s / 1e9, 1)}
-    counts = None
-    if os.path.exists(PROFILE_COUNTS):
-        counts = json.load(open(PROFILE_COUNTS))
+    counts = load_counts(PROFILE_COUNTS)
     if counts and counts.get("valu_insts_per_image"):
         ops = counts["valu_insts_per_image"] * 64.0 * B
         batch_diag["valu_busy"] = round(ops / kern_s / VALU_INT32_PEAK, 4)
