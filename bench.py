@@ -3,6 +3,7 @@
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--plain P]
                 [--serve-seconds S] [--mixed-seconds M] [--no-serve] [--no-cpu]
 python bench.py --only-edt      (the 4096x4096 exact EDT alone, for profiling)
+python bench.py --only-volumes  (the 3D leg alone, for profiling)
 
 A step filters one batch of B synthetic 512x512 images (the 40-shape recipe
 with a 200-pixel constraint set each) in one persistent launch
@@ -121,6 +122,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-edt", action="store_true")
+    ap.add_argument("--only-volumes", action="store_true")
     return ap.parse_args()
 
 
@@ -419,6 +421,37 @@ def bench_labels(ctx, reps=5):
             "Mpixel_per_s": round(n * Hn * Wn / ms / 1e3, 2)}
 
 
+def bench_volumes(ctx, reps=3):
+    """3D HASF ((26,6)) on a batch of 256 volumes of 64^3 at r = 3 (balls with
+    cavities and 2 % noise, 16 distinct volumes): one hasf_filter3_batch launch
+    per call, inputs restored before each call outside the timed region (the
+    3D oracle is timed in the CPU baseline leg)."""
+    import torch
+    from paper_1603_09337_amd import synth
+    vols, r = synth.workload_volumes()
+    src = [torch.from_numpy(v).cuda() for v in vols[:16]]
+    work = [src[k % 16].clone() for k in range(len(vols))]
+    items = [(w, None, r) for w in work]
+    ctx.filter3_batch(items)
+    ctx.sync()
+    stream = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        for k, w in enumerate(work):
+            w.copy_(src[k % 16])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.filter3_batch(items)
+        e1.record(stream)
+        ctx.sync()
+        ts.append(e0.elapsed_time(e1))
+    ms = min(ts)
+    nvox = sum(v.size for v in vols)
+    return {"workload": "hasf_filter3_batch: 256 volumes of 64^3, r = 3, (26,6), balls with cavities, 2 % noise",
+            "ms": round(ms, 2), "volumes_per_s": round(len(vols) / ms * 1e3, 1),
+            "Mvoxel_per_s": round(nvox / ms / 1e3, 1)}
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -467,7 +500,16 @@ def cpu_baseline(Xs, Cs, n, distinct):
         pool.map(_oracle_share, shares)
         t3 = time.perf_counter()
     multi = cores * per * H * W / (t3 - t2) / 1e6
+    # the 3D oracle on one volume of the 3D leg's workload, one core
+    from paper_1603_09337_amd import synth
+    vols, r3 = synth.workload_volumes(n=1)
+    log("cpu oracle: one 64^3 volume, r=3")
+    t4 = time.perf_counter()
+    oracle.hasf3(vols[0], None, r3)
+    t5 = time.perf_counter()
     return {"value": round(multi, 3), "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
+            "volumes_one_core": {"value": round(vols[0].size / (t5 - t4) / 1e6, 4), "unit": "Mvoxel/s",
+                                 "sample": "one 64^3 volume of the 3D leg, r = 3", "cores": 1},
             "frames_per_s": round(cores * per / (t3 - t2), 3),
             "sample": "%d of the 512x512 r=5 images (C = 200 px), %d per process on %d processes; "
                       "one core: %d images" % (cores * per, per, cores, n),
@@ -495,6 +537,9 @@ def main():
     ctx = hasf.Context(0)
     if a.only_edt:
         print(json.dumps({"edt": bench_edt(ctx, reps=a.steps)}), flush=True)
+        return
+    if a.only_volumes:
+        print(json.dumps({"volumes": bench_volumes(ctx, reps=a.steps)}), flush=True)
         return
     Xs, Cs = make_inputs(a.distinct)
     B = a.batch
@@ -572,6 +617,8 @@ def main():
     large = bench_large(ctx)
     log("labels 512x512, 16 labels")
     labels = bench_labels(ctx)
+    log("volumes 256 x 64^3 r=3")
+    volumes = bench_volumes(ctx)
 
     served = None
     if not a.no_serve:
@@ -613,6 +660,7 @@ def main():
         "edt": edt,
         "large": large,
         "labels": labels,
+        "volumes": volumes,
         "batch_kernel": batch_diag,
         "roofline": large["roofline"],
         "cpu_baseline": cpu,

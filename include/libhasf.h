@@ -308,7 +308,7 @@ hasf_status hasf_filter_batch(hasf_ctx* ctx, const hasf_image* imgs, int n);
  * Limits: D, H, W >= 1, D H W < 2^31, 0 <= r <= HASF_R_MAX. hasf_filter3_batch
  * filters n volumes in one launch (a workgroup per volume at a time), the
  * descriptor array being a host array copied before the call returns; the
- * library allocates 5 D H W bytes of scratch per volume.
+ * library allocates about 9 D H W bytes of scratch per volume.
  */
 typedef struct {
     uint8_t* X;        /* device, in/out */

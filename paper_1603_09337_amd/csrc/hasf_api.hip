@@ -847,7 +847,7 @@ hasf_status hasf_filter3_batch(hasf_ctx* ctx, const hasf_volume* vols, int n)
             set_err(ctx, "%s: volume %d: r = %d outside [0, %d]", what, k, v.r, HASF_R_MAX);
             return HASF_EINVAL;
         }
-        bytes += align256(5 * (size_t)v.D * v.H * v.W);
+        bytes += align256(9 * (size_t)v.D * v.H * v.W + 4);
     }
     if (n == 0)
         return HASF_OK;
@@ -871,7 +871,7 @@ hasf_status hasf_filter3_batch(hasf_ctx* ctx, const hasf_volume* vols, int n)
         d[k].W = vols[k].W;
         d[k].r = vols[k].r;
         d[k].work = (uint8_t*)(base + off);
-        off += align256(5 * (size_t)vols[k].D * vols[k].H * vols[k].W);
+        off += align256(9 * (size_t)vols[k].D * vols[k].H * vols[k].W + 4);
     }
     hipError_t e = hipMemcpyAsync(base, host, meta, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess)

@@ -157,7 +157,8 @@ struct GridCtl {
 };
 
 // One volume of a 3D batch: the caller's planes and this launch's work planes
-// (S, A, K and two distance planes, D * H * W bytes each).
+// (S, A, K and two distance planes, D * H * W bytes each, then D * H * W
+// 32-bit candidate entries).
 struct VolDesc {
     uint8_t* X;
     const uint8_t* C;

@@ -117,6 +117,7 @@ struct Vol {
     uint8_t* K;
     uint8_t* G;  // distance work plane
     uint8_t* P;  // squared distance, saturated (VFAR beyond i^2)
+    uint32_t* E; // the phase's candidates by (parity class, level)
     int D, H, W;
     long long N;
 };
@@ -209,7 +210,21 @@ __device__ __forceinline__ bool vol_cand(const Vol& v, long long q, int mode)
     }
 }
 
-__device__ void vol_phase(const Vol& v, int i, int mode, unsigned* cnt, int* s_flag)
+// parity class of a voxel: (z mod 2, y mod 2, x mod 2) in lexicographic order
+__device__ __forceinline__ int vol_class(const Vol& v, long long q)
+{
+    const int x = (int)(q % v.W);
+    const long long zy = q / v.W;
+    const int y = (int)(zy % v.H), z = (int)(zy / v.H);
+    return ((z & 1) << 2) | ((y & 1) << 1) | (x & 1);
+}
+
+// One phase at radius i. The candidates within i^2 are listed once, sorted
+// by (parity class, level) with a counting sort, so that the candidates of
+// class c at levels <= d are one contiguous run of the list; a pass of level
+// d over class c then visits that run only (the voxels that are not, or no
+// longer, candidates fail the test at once).
+__device__ void vol_phase(const Vol& v, int i, int mode, unsigned* cnt, unsigned* off, int* s_flag)
 {
     const bool thin = mode == 0 || mode == 3;
     if (mode == 0 || mode == 2) {
@@ -218,33 +233,52 @@ __device__ void vol_phase(const Vol& v, int i, int mode, unsigned* cnt, int* s_f
     }
     vol_distance(v, i, thin);
     const int r2 = i * i;
-    for (int k = threadIdx.x; k <= r2; k += VOL_NT)
+    const int nl = r2 + 1;  // levels 0..i^2
+    const int nk = 8 * nl;  // keys: class * nl + level
+    for (int k = threadIdx.x; k < nk; k += VOL_NT)
         cnt[k] = 0;
     __syncthreads();
     for (long long q = threadIdx.x; q < v.N; q += VOL_NT)
         if (v.P[q] != VFAR && vol_cand(v, q, mode))
-            atomicAdd(cnt + v.P[q], 1u);
+            atomicAdd(cnt + vol_class(v, q) * nl + v.P[q], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned o = 0;
+        for (int k = 0; k < nk; ++k) {
+            off[k] = o;
+            o += cnt[k];
+            cnt[k] = 0;  // becomes the fill count of the key
+        }
+        off[nk] = o;
+    }
+    __syncthreads();
+    for (long long q = threadIdx.x; q < v.N; q += VOL_NT)
+        if (v.P[q] != VFAR && vol_cand(v, q, mode)) {
+            const int k = vol_class(v, q) * nl + v.P[q];
+            v.E[off[k] + atomicAdd(cnt + k, 1u)] = (uint32_t)q;
+        }
     __syncthreads();
     for (int d = 0; d <= r2; ++d) {
-        if (cnt[d] == 0)
+        bool any_level = false;
+        for (int c = 0; c < 8; ++c)
+            any_level |= off[c * nl + d + 1] > off[c * nl + d];
+        if (!any_level)
             continue;  // uniform: no candidate at this level
         for (;;) {
             if (threadIdx.x == 0)
                 *s_flag = 0;
             __syncthreads();
-            int any = 0;
-            for (int sf = 0; sf < 8; ++sf) {
-                const int pz = sf >> 2, py = (sf >> 1) & 1, px = sf & 1;
-                const int nz = (v.D - pz + 1) >> 1, ny = (v.H - py + 1) >> 1, nx = (v.W - px + 1) >> 1;
-                const long long ns = (long long)nz * ny * nx;
+            for (int c = 0; c < 8; ++c) {
+                const unsigned t0 = off[c * nl], t1 = off[c * nl + d + 1];
                 bool changed = false;
-                for (long long t = threadIdx.x; t < ns; t += VOL_NT) {
-                    const int ix = (int)(t % nx);
-                    const long long t2 = t / nx;
-                    const int iy = (int)(t2 % ny), iz = (int)(t2 / ny);
-                    const int z = 2 * iz + pz, y = 2 * iy + py, x = 2 * ix + px;
-                    const long long q = ((long long)z * v.H + y) * v.W + x;
-                    if (v.P[q] <= d && vol_cand(v, q, mode) && simple26(vol_code(v, z, y, x))) {
+                for (unsigned t = t0 + threadIdx.x; t < t1; t += VOL_NT) {
+                    const long long q = v.E[t];
+                    if (!vol_cand(v, q, mode))
+                        continue;  // changed in an earlier pass of this phase
+                    const int x = (int)(q % v.W);
+                    const long long zy = q / v.W;
+                    const int y = (int)(zy % v.H), z = (int)(zy / v.H);
+                    if (simple26(vol_code(v, z, y, x))) {
                         v.S[q] = thin ? 0 : 1;
                         changed = true;
                     }
@@ -255,7 +289,7 @@ __device__ void vol_phase(const Vol& v, int i, int mode, unsigned* cnt, int* s_f
                 __threadfence_block();
                 __syncthreads();
             }
-            any = *s_flag;
+            const int any = *s_flag;
             __syncthreads();
             if (!any)
                 break;
@@ -269,7 +303,8 @@ __device__ void vol_phase(const Vol& v, int i, int mode, unsigned* cnt, int* s_f
 __global__ __launch_bounds__(VOL_NT) void hasf_vol_kernel(const VolDesc* __restrict__ desc, int n,
                                                           int* __restrict__ next)
 {
-    __shared__ unsigned cnt[HASF_R_MAX * HASF_R_MAX + 1];
+    __shared__ unsigned cnt[8 * (HASF_R_MAX * HASF_R_MAX + 1)];
+    __shared__ unsigned off[8 * (HASF_R_MAX * HASF_R_MAX + 1) + 1];
     __shared__ int s_img, s_flag;
     for (;;) {
         if (threadIdx.x == 0)
@@ -290,6 +325,7 @@ __global__ __launch_bounds__(VOL_NT) void hasf_vol_kernel(const VolDesc* __restr
         v.K = d.work + 2 * v.N;
         v.G = d.work + 3 * v.N;
         v.P = d.work + 4 * v.N;
+        v.E = reinterpret_cast<uint32_t*>(d.work + ((5 * v.N + 3) & ~3ll));  // the block is 256-byte aligned
         for (long long q = threadIdx.x; q < v.N; q += VOL_NT) {
             const uint8_t x = d.X[q] != 0;
             v.S[q] = x;
@@ -298,7 +334,7 @@ __global__ __launch_bounds__(VOL_NT) void hasf_vol_kernel(const VolDesc* __restr
         __syncthreads();
         for (int i = 1; i <= d.r; ++i)
             for (int mode = 0; mode < 4; ++mode)
-                vol_phase(v, i, mode, cnt, &s_flag);
+                vol_phase(v, i, mode, cnt, off, &s_flag);
         for (long long q = threadIdx.x; q < v.N; q += VOL_NT)
             d.X[q] = v.S[q];
         __syncthreads();

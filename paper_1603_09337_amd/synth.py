@@ -34,6 +34,7 @@ SEED_SHAPES = 1603093372
 SEED_LARGE = 1603093373
 SEED_BATCH = 1603093374
 SEED_STREAM = 1603093375
+SEED_VOLUMES = 1603093376
 
 
 def _rng(seed: int) -> np.random.Generator:
@@ -217,3 +218,28 @@ def label_image(H, W, n_labels, seed, n_sites=None, noise=0.01):
     flip = rng.random((H, W)) < noise
     out[flip] = rng.integers(0, n_labels, int(flip.sum())).astype(np.uint8)
     return out
+
+
+def balls_volume(D, H, W, seed, n=8, noise=0.02):
+    """3D stand-in (the paper gives no 3D workload): the union of n balls of
+    radius U[3, 0.3 min(D, H, W)] (every third one hollow: a cavity of 0.45
+    of its radius), then a fraction `noise` of the voxels flipped."""
+    rng = _rng(seed)
+    zz, yy, xx = np.mgrid[0:D, 0:H, 0:W]
+    V = np.zeros((D, H, W), bool)
+    for k in range(n):
+        c = rng.uniform(0, (D, H, W))
+        R = rng.uniform(3, max(3.5, 0.3 * min(D, H, W)))
+        d2 = (zz - c[0]) ** 2 + (yy - c[1]) ** 2 + (xx - c[2]) ** 2
+        b = d2 <= R * R
+        if k % 3 == 2:
+            b &= d2 > (0.45 * R) ** 2
+        V |= b
+    return (V ^ (rng.random(V.shape) < noise)).astype(np.uint8)
+
+
+def workload_volumes(n=256, S=64, seed=SEED_VOLUMES, distinct=16):
+    """The 3D benchmark workload: n volumes of S^3 (cycling through `distinct`
+    drawn ones), r = 3."""
+    bank = [balls_volume(S, S, S, seed + k) for k in range(distinct)]
+    return [bank[k % distinct] for k in range(n)], 3

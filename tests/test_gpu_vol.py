@@ -12,7 +12,7 @@ import torch
 import oracle
 import topo3_checks as t3
 from gpu_util import ctx, say
-from paper_1603_09337_amd import hasf
+from paper_1603_09337_amd import hasf, synth
 
 pytestmark = pytest.mark.gpu
 
@@ -29,17 +29,7 @@ def _run(V, C, r):
 
 
 def balls(D, H, W, seed, n=5):
-    rng = np.random.default_rng(seed)
-    zz, yy, xx = np.mgrid[0:D, 0:H, 0:W]
-    V = np.zeros((D, H, W), bool)
-    for k in range(n):
-        c = rng.uniform(0, (D, H, W))
-        R = rng.uniform(1.5, max(2.5, 0.35 * min(D, H, W)))
-        b = (zz - c[0]) ** 2 + (yy - c[1]) ** 2 + (xx - c[2]) ** 2 <= R * R
-        if k % 3 == 2:
-            b &= (zz - c[0]) ** 2 + (yy - c[1]) ** 2 + (xx - c[2]) ** 2 > (0.45 * R) ** 2
-        V |= b
-    return (V ^ (rng.random(V.shape) < 0.03)).astype(np.uint8)
+    return synth.balls_volume(D, H, W, seed, n=n, noise=0.03)
 
 
 CASES = [
