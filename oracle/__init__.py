@@ -18,6 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hasf_oracle.c")
 _SRC3 = os.path.join(_HERE, "hasf_oracle3d.c")
+_SRCW = os.path.join(_HERE, "hasf_oracle_wshed.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -30,7 +31,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC",
-                               "-o", tmp, _SRC, _SRC3])
+                               "-o", tmp, _SRC, _SRC3, _SRCW])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -39,7 +40,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC), os.path.getmtime(_SRC3)):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in (_SRC, _SRC3, _SRCW)):
         build(force=True)
     lib = ctypes.CDLL(_LIB)
     lib.oracle_simple_lut.argtypes = [ctypes.c_int, U8P]
@@ -81,6 +82,8 @@ def _load():
     lib.oracle3_schedule.restype = ctypes.c_long
     lib.oracle3_hasf.argtypes = [U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, U8P]
     lib.oracle3_hasf.restype = ctypes.c_long
+    lib.oracle_wshed.argtypes = [U8P, ctypes.c_int, ctypes.c_int]
+    lib.oracle_wshed.restype = ctypes.c_long
     lib.oracle_hasf_queue.argtypes = [U8P, U8P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.oracle_hasf_queue.restype = ctypes.c_long
     _lib = lib
@@ -291,3 +294,14 @@ def hasf_labels(Lab, values, r: int):
     array of 0/1 planes, one per value, in the order given."""
     lab = np.ascontiguousarray(Lab, dtype=np.uint8)
     return np.stack([hasf((lab == np.uint8(v)).astype(np.uint8), None, r) for v in values])
+
+
+def wshed(F):
+    """The topological watershed's lowering (grey-level W-thinning, lower
+    sections 4-connected) of the uint8 grey-level image F, to stability, on the
+    subfield schedule: returns the lowered image."""
+    f = np.ascontiguousarray(F, dtype=np.uint8).copy()
+    n = _load().oracle_wshed(f.ctypes.data_as(U8P), *f.shape)
+    if n < 0:
+        raise ValueError("oracle wshed: bad arguments")
+    return f

@@ -35,6 +35,7 @@ SEED_LARGE = 1603093373
 SEED_BATCH = 1603093374
 SEED_STREAM = 1603093375
 SEED_VOLUMES = 1603093376
+SEED_GREY = 1603093377
 
 
 def _rng(seed: int) -> np.random.Generator:
@@ -243,3 +244,22 @@ def workload_volumes(n=256, S=64, seed=SEED_VOLUMES, distinct=16):
     drawn ones), r = 3."""
     bank = [balls_volume(S, S, S, seed + k) for k in range(distinct)]
     return [bank[k % distinct] for k in range(n)], 3
+
+
+def grey_image(H, W, seed, n_bumps=None, noise=6.0):
+    """Grey-level stand-in for the watershed (the paper gives no grey-level
+    workload): a sum of Gaussian bumps and pits (amplitude U[-1, 1], width
+    U[4, max(5, min(H, W) / 4)], about one per 4000 pixels) scaled to 0..255,
+    plus Gaussian noise of deviation `noise`, rounded and clipped."""
+    rng = _rng(seed)
+    n = n_bumps if n_bumps is not None else max(4, (H * W) // 4000)
+    yy, xx = np.mgrid[0:H, 0:W]
+    F = np.zeros((H, W))
+    for _ in range(n):
+        cy, cx = rng.uniform(0, H), rng.uniform(0, W)
+        s = rng.uniform(4, max(5.0, min(H, W) / 4))
+        a = rng.uniform(-1, 1)
+        F += a * np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * s * s))
+    lo, hi = F.min(), F.max()
+    F = (F - lo) / (hi - lo + 1e-12) * (255 - 2 * noise) + noise + rng.normal(0, noise, F.shape)
+    return np.clip(np.rint(F), 0, 255).astype(np.uint8)
