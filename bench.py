@@ -4,6 +4,7 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B] [--plain P]
                 [--serve-seconds S] [--mixed-seconds M] [--no-serve] [--no-cpu]
 python bench.py --only-edt      (the 4096x4096 exact EDT alone, for profiling)
 python bench.py --only-volumes  (the 3D leg alone, for profiling)
+python bench.py --only-watershed (the watershed leg alone, for profiling)
 
 A step filters one batch of B synthetic 512x512 images (the 40-shape recipe
 with a 200-pixel constraint set each) in one persistent launch
@@ -123,6 +124,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-edt", action="store_true")
     ap.add_argument("--only-volumes", action="store_true")
+    ap.add_argument("--only-watershed", action="store_true")
     return ap.parse_args()
 
 
@@ -452,6 +454,39 @@ def bench_volumes(ctx, reps=3):
             "Mvoxel_per_s": round(nvox / ms / 1e3, 1)}
 
 
+def bench_watershed(ctx, reps=3):
+    """The topological watershed's lowering on 64 grey-level 512x512 images
+    (synth.grey_image: Gaussian bumps and pits with noise, 16 distinct) in one
+    hasf_watershed_batch launch per call, inputs restored before each call
+    outside the timed region; and one image alone."""
+    import torch
+    from paper_1603_09337_amd import synth
+    n, Hn, Wn = 64, 512, 512
+    bank = [torch.from_numpy(synth.grey_image(Hn, Wn, synth.SEED_GREY + k)).cuda() for k in range(16)]
+    work = [bank[k % 16].clone() for k in range(n)]
+    ctx.watershed_batch(work)
+    ctx.sync()
+    stream = torch.cuda.current_stream()
+
+    def timed(imgs, src):
+        ts = []
+        for _ in range(reps):
+            for k, w in enumerate(imgs):
+                w.copy_(src[k % len(src)])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.watershed_batch(imgs)
+            e1.record(stream)
+            ctx.sync()
+            ts.append(e0.elapsed_time(e1))
+        return min(ts)
+    ms = timed(work, bank)
+    one = timed(work[:1], bank[:1])
+    return {"workload": "hasf_watershed_batch: 64 grey-level 512x512 images (Gaussian bumps and pits, noise)",
+            "ms": round(ms, 2), "images_per_s": round(n / ms * 1e3, 1),
+            "Mpixel_per_s": round(n * Hn * Wn / ms / 1e3, 1), "one_image_ms": round(one, 2)}
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -500,7 +535,13 @@ def cpu_baseline(Xs, Cs, n, distinct):
         pool.map(_oracle_share, shares)
         t3 = time.perf_counter()
     multi = cores * per * H * W / (t3 - t2) / 1e6
-    # the 3D oracle on one volume of the 3D leg's workload, one core
+    # the watershed oracle on one image of the watershed leg, one core
+    Gw = synth.grey_image(512, 512, synth.SEED_GREY)
+    log("cpu oracle: one 512x512 watershed")
+    t6 = time.perf_counter()
+    oracle.wshed(Gw)
+    t7 = time.perf_counter()
+        # the 3D oracle on one volume of the 3D leg's workload, one core
     from paper_1603_09337_amd import synth
     vols, r3 = synth.workload_volumes(n=1)
     log("cpu oracle: one 64^3 volume, r=3")
@@ -508,6 +549,8 @@ def cpu_baseline(Xs, Cs, n, distinct):
     oracle.hasf3(vols[0], None, r3)
     t5 = time.perf_counter()
     return {"value": round(multi, 3), "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
+            "watershed_one_core": {"value": round(Gw.size / (t7 - t6) / 1e6, 4), "unit": "Mpixel/s",
+                                   "sample": "one 512x512 image of the watershed leg", "cores": 1},
             "volumes_one_core": {"value": round(vols[0].size / (t5 - t4) / 1e6, 4), "unit": "Mvoxel/s",
                                  "sample": "one 64^3 volume of the 3D leg, r = 3", "cores": 1},
             "frames_per_s": round(cores * per / (t3 - t2), 3),
@@ -540,6 +583,9 @@ def main():
         return
     if a.only_volumes:
         print(json.dumps({"volumes": bench_volumes(ctx, reps=a.steps)}), flush=True)
+        return
+    if a.only_watershed:
+        print(json.dumps({"watershed": bench_watershed(ctx, reps=a.steps)}), flush=True)
         return
     Xs, Cs = make_inputs(a.distinct)
     B = a.batch
@@ -619,6 +665,8 @@ def main():
     labels = bench_labels(ctx)
     log("volumes 256 x 64^3 r=3")
     volumes = bench_volumes(ctx)
+    log("watershed 64 x 512x512")
+    watershed = bench_watershed(ctx)
 
     served = None
     if not a.no_serve:
@@ -661,6 +709,7 @@ def main():
         "large": large,
         "labels": labels,
         "volumes": volumes,
+        "watershed": watershed,
         "batch_kernel": batch_diag,
         "roofline": large["roofline"],
         "cpu_baseline": cpu,

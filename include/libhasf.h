@@ -320,6 +320,32 @@ hasf_status hasf_filter3(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, int D, int
 hasf_status hasf_filter3_batch(hasf_ctx* ctx, const hasf_volume* vols, int n);
 
 /*
+ * The topological watershed's lowering (grey-level W-thinning), in place.
+ * Sec. 3.1 places the topological watershed in the class of topology-based
+ * operators the filter belongs to, without defining it; the operator is the
+ * classical grey-level one on the (8,4) pair of Sec. 2. F is a grey-level
+ * image (H rows of ld bytes, levels 0..255); lower sections {p : F(p) < k}
+ * are 4-connected and the outside of the window belongs to none. A pixel is
+ * W-destructible when it has a lower neighbour and the lower pixels of its
+ * 8-neighbourhood 4-adjacent to it lie in one 4-component of them (T-bar = 1);
+ * it is then lowered to the largest level of its lower neighbours. Rounds of
+ * four passes over the 2x2 parity subfields of (row, column) run until a
+ * round lowers nothing: the result is a fixed point, only lowers pixels, and
+ * at every level k each 4-component of {F' < k} holds exactly one of {F < k}
+ * (no merge of basins, no new minimum). Limits: H, W >= 1, H W < 2^31.
+ * hasf_watershed_batch lowers n images in one launch (a workgroup per image at
+ * a time; the descriptor array is a host array copied before the call
+ * returns).
+ */
+typedef struct {
+    uint8_t* F;   /* device, in/out */
+    int H, W;
+    int64_t ld;
+} hasf_gimage;
+hasf_status hasf_watershed(hasf_ctx* ctx, uint8_t* F, int H, int W, int64_t ld);
+hasf_status hasf_watershed_batch(hasf_ctx* ctx, const hasf_gimage* imgs, int n);
+
+/*
  * Per-label smoothing of a label (grey-level) image: the binary method of
  * Sec. 2 applied to each label as its own object set (Sec. 3.1 places
  * grey-level topological operators in the same class; the paper smooths

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_lib", "libhasf.so")
 SOURCES = ["hasf_api.hip", "hasf_filter.hip", "hasf_tile.hip", "hasf_edt.hip", "hasf_topo.hip", "hasf_serve.hip",
-           "hasf_vol.hip"]
+           "hasf_vol.hip", "hasf_wshed.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

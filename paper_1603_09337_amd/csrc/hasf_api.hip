@@ -24,6 +24,9 @@ hipError_t launch_tile(const ImgDesc* d_desc, TileCtl* d_ctl, unsigned* d_err, c
 hipError_t noalloc_init(int device);
 void* noalloc_scratch(int device);
 hipError_t launch_vol(const VolDesc* d_desc, int n, int* d_next, int grid, hipStream_t stream);
+size_t wshed_lds_bytes(int H, int W);
+size_t wshed_lds_max();
+hipError_t launch_wshed(const GreyDesc* d_desc, int n, int* d_next, int grid, size_t lds, hipStream_t stream);
 }  // namespace hasf_detail
 
 using namespace hasf_detail;
@@ -882,6 +885,69 @@ hasf_status hasf_filter3_batch(hasf_ctx* ctx, const hasf_volume* vols, int n)
     if (e != hipSuccess)
         return dev_fail(ctx, e, "hasf_vol_kernel launch");
     return HASF_OK;
+}
+
+hasf_status hasf_watershed_batch(hasf_ctx* ctx, const hasf_gimage* imgs, int n)
+{
+    const char* what = "hasf_watershed_batch";
+    if (!ctx) {
+        set_err(nullptr, "%s: ctx is NULL", what);
+        return HASF_EINVAL;
+    }
+    if (n < 0 || (n > 0 && !imgs)) {
+        set_err(ctx, "%s: bad image array", what);
+        return HASF_EINVAL;
+    }
+    for (int k = 0; k < n; ++k) {
+        const hasf_gimage& g = imgs[k];
+        if (!g.F || g.H < 1 || g.W < 1 || g.ld < g.W || (long long)g.H * g.W >= (1ll << 31)) {
+            set_err(ctx, "%s: image %d: need F != NULL, H, W >= 1, ld >= W and H W < 2^31", what, k);
+            return HASF_EINVAL;
+        }
+    }
+    if (n == 0)
+        return HASF_OK;
+    hipSetDevice(ctx->device);
+    const size_t meta = align256(256 + sizeof(GreyDesc) * (size_t)n);
+    hasf_status s = ensure_scratch(ctx, meta);
+    if (s)
+        return s;
+    char* base = (char*)ctx->scratch;
+    char* host = nullptr;
+    if ((s = stage_buffer(ctx, meta, &host)))
+        return s;
+    std::memset(host, 0, meta);  // the queue counter starts at 0
+    GreyDesc* d = (GreyDesc*)(host + 256);
+    size_t lds = 0;
+    for (int k = 0; k < n; ++k) {
+        d[k].F = imgs[k].F;
+        d[k].ld = imgs[k].ld;
+        d[k].H = imgs[k].H;
+        d[k].W = imgs[k].W;
+        const size_t need = wshed_lds_bytes(imgs[k].H, imgs[k].W);
+        d[k].flags = need <= wshed_lds_max() ? 1 : 0;
+        if (d[k].flags)
+            lds = std::max(lds, need);
+    }
+    hipError_t e = hipMemcpyAsync(base, host, meta, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev_stage, ctx->stream);
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "hipMemcpyAsync(image descriptors)");
+    e = launch_wshed((const GreyDesc*)(base + 256), n, (int*)base, std::min(n, ctx->num_cu * 2), lds, ctx->stream);
+    if (e != hipSuccess)
+        return dev_fail(ctx, e, "hasf_wshed_kernel launch");
+    return HASF_OK;
+}
+
+hasf_status hasf_watershed(hasf_ctx* ctx, uint8_t* F, int H, int W, int64_t ld)
+{
+    hasf_gimage g;
+    g.F = F;
+    g.H = H;
+    g.W = W;
+    g.ld = ld;
+    return hasf_watershed_batch(ctx, &g, 1);
 }
 
 hasf_status hasf_filter3(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, int D, int H, int W, int r)

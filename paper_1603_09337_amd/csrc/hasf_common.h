@@ -156,6 +156,15 @@ struct GridCtl {
     unsigned cnt[HASF_LEVELS_MAX];
 };
 
+// One grey-level image of a watershed batch (in place); flags: the kernel
+// keeps its per-word flags in LDS (else it tests every word of every pass).
+struct GreyDesc {
+    uint8_t* F;
+    long long ld;
+    int H, W;
+    int flags;
+};
+
 // One volume of a 3D batch: the caller's planes and this launch's work planes
 // (S, A, K and two distance planes, D * H * W bytes each, then D * H * W
 // 32-bit candidate entries).

@@ -54,6 +54,10 @@ class _Volume(ctypes.Structure):
                 ("W", ctypes.c_int), ("r", ctypes.c_int)]
 
 
+class _GImage(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_void_p), ("H", ctypes.c_int), ("W", ctypes.c_int), ("ld", ctypes.c_int64)]
+
+
 class _ServeOpts(ctypes.Structure):
     _fields_ = [("pool_bytes", ctypes.c_size_t), ("lanes", ctypes.c_int), ("max_batch", ctypes.c_int),
                 ("max_pending", ctypes.c_int), ("flags", ctypes.c_uint), ("express_lanes", ctypes.c_int),
@@ -105,6 +109,8 @@ _lib.hasf_filter_cd.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, 
                                 ctypes.c_int]
 _lib.hasf_filter_batch.argtypes = [_vp, ctypes.POINTER(_Image), ctypes.c_int]
 _lib.hasf_filter3_batch.argtypes = [_vp, ctypes.POINTER(_Volume), ctypes.c_int]
+_lib.hasf_watershed_batch.argtypes = [_vp, ctypes.POINTER(_GImage), ctypes.c_int]
+_lib.hasf_watershed.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64]
 _lib.hasf_filter3.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
 _lib.hasf_filter_inf.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
                                  ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.POINTER(ctypes.c_int)]
@@ -114,7 +120,8 @@ _lib.hasf_filter_labels.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes
 for _f in ("hasf_create", "hasf_set_stream", "hasf_sync", "hasf_simple_lut", "hasf_edt_sq", "hasf_edt_sq_noalloc",
            "hasf_homotopic_thin", "hasf_homotopic_thicken", "hasf_homotopic_thin_conn",
            "hasf_homotopic_thicken_conn", "hasf_filter", "hasf_filter_cd",
-           "hasf_filter_batch", "hasf_filter_labels", "hasf_filter_inf", "hasf_filter3", "hasf_filter3_batch"):
+           "hasf_filter_batch", "hasf_filter_labels", "hasf_filter_inf", "hasf_filter3", "hasf_filter3_batch",
+           "hasf_watershed", "hasf_watershed_batch"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -321,6 +328,20 @@ class Context:
 
     def filter3(self, X, C=None, r: int = 1):
         return self.filter3_batch([(X, C, r)])[0]
+
+    def watershed_batch(self, images):
+        """The topological watershed's lowering (grey-level W-thinning) of each
+        2D uint8 CUDA tensor (row pitch allowed), in place, in one launch."""
+        arr = (_GImage * max(1, len(images)))()
+        for k, F in enumerate(images):
+            H, W, ld = _img(F, "F[%d]" % k, self.device)
+            arr[k] = _GImage(F.data_ptr(), H, W, ld)
+        self._stream()
+        self._check(_lib.hasf_watershed_batch(self._h, arr, len(images)))
+        return images
+
+    def watershed(self, F):
+        return self.watershed_batch([F])[0]
 
     def plan_batch(self, items):
         """Prepare the descriptor array of a batch once (the tensors must stay alive).
