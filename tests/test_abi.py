@@ -54,6 +54,9 @@ def test_null_context_is_rejected_before_device_work():
     assert lib.hasf_edt_sq(None, p, 8, 8, 8, 0, p, 8) == hasf.HASF_EINVAL
     assert lib.hasf_homotopic_thin(None, p, None, 8, 8, 8) == hasf.HASF_EINVAL
     assert lib.hasf_homotopic_thicken(None, p, p, 8, 8, 8) == hasf.HASF_EINVAL
+    assert lib.hasf_filter3(None, p, None, 4, 4, 4, 1) == hasf.HASF_EINVAL
+    assert lib.hasf_watershed(None, p, 8, 8, 8) == hasf.HASF_EINVAL
+    assert lib.hasf_watershed_batch(None, None, 1) == hasf.HASF_EINVAL
     assert lib.hasf_set_stream(None, None) == hasf.HASF_EINVAL
     assert lib.hasf_sync(None) == hasf.HASF_EINVAL
     assert b"ctx" in lib.hasf_last_error(None)
