@@ -181,8 +181,12 @@ struct VolDesc {
 // barrier parity), and per phase (4 per radius) and level whether some tile
 // has candidates.
 struct TileCtl {
-    unsigned bar_count, pad0[63];
-    unsigned bar_gen, pad1[63];
+    // arrivals (low half) and arrivals that report a change (high half),
+    // summed over all barriers
+    unsigned long long bar_arrive, pad0[31];
+    // barriers completed (low half) and the high half of bar_arrive when the
+    // last one completed
+    unsigned long long bar_word, pad1[31];
     unsigned abort, err, pad2[62];
     unsigned last_change[2], pad3[62];
     unsigned lev[4 * HASF_R_MAX][HASF_LEVELS_MAX];

@@ -43,47 +43,93 @@ struct TileSync {
     unsigned nblk;
     unsigned gen;     // barriers passed (uniform)
     unsigned round;   // rounds run in this launch (uniform)
-    unsigned rounds;  // rounds of the schedule (uniform)
+    unsigned rounds;  // rounds of the schedule (thread 0 of workgroup 0)
     unsigned acts;    // levels activated (uniform)
+    unsigned cchg;    // high half of the barrier word last seen (thread 0)
 };
 
-// Grid barrier: every wave waits for its own stores; one thread per
-// workgroup releases them at device scope, counts the workgroup in, waits
-// for the last arrival's generation bump and acquires. Bounded: on time-out,
-// or when another workgroup gave up, it returns false.
-__device__ __forceinline__ bool tile_sync(TileSync& ts, int* s_ok)
+// Grid barrier. Every wave first waits until its own stores have completed;
+// then one thread per workgroup counts the workgroup in and waits for the
+// last arrival to publish the new generation. Bounded: on time-out, or when
+// another workgroup gave up, it returns false.
+//
+// `fenced` (the barriers around the distance stages): a device-scope release
+// before the arrival and an acquire after it, so that the plain stores of the
+// row-major planes are visible to every later plain load. The epoch barriers
+// go without them: the only data that crosses them, the exchange copies, is
+// written and read with device-scope atomic stores and loads, which are
+// coherent across the XCDs' L2 caches by themselves, and a store counts as
+// complete for the wait only once it is visible at that scope. Skipping the
+// fences keeps each L2's lines (level entries, planes) valid and spares the
+// write-back of its dirty lines at every epoch.
+//
+// `chg` (uniform): this tile's last round changed one of its own rows. Such
+// arrivals are counted in the high half of the arrival word, and the last
+// arrival copies the running count into the barrier word, so each tile
+// learns without another memory round trip whether any tile did: *s_quiet
+// is 1 when none did.
+__device__ __forceinline__ bool tile_sync(TileSync& ts, int* s_ok, bool fenced, bool chg = false,
+                                          int* s_quiet = nullptr)
 {
     __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
     __syncthreads();
     if (threadIdx.x == 0) {
         TileCtl* tc = ts.tc;
         int ok = 1;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned target = (ts.gen + 1) * ts.nblk;
-        const unsigned old = __hip_atomic_fetch_add(&tc->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (old + 1 == target) {
-            __hip_atomic_store(&tc->bar_gen, ts.gen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (fenced)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned long long add = 1ull | ((unsigned long long)(chg ? 1u : 0u) << 32);
+        const unsigned long long old =
+            __hip_atomic_fetch_add(&tc->bar_arrive, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long word;
+        if ((unsigned)old + 1u == (ts.gen + 1) * ts.nblk) {
+            word = (unsigned long long)(ts.gen + 1) | ((old + add) & 0xFFFFFFFF00000000ull);
+            __hip_atomic_store(&tc->bar_word, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const unsigned long long t0 = wall_clock64();
-            while (__hip_atomic_load(&tc->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ts.gen) {
-                if (__hip_atomic_load(&tc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    ok = 0;
+            for (unsigned it = 1;; ++it) {
+                word = __hip_atomic_load(&tc->bar_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((unsigned)word != ts.gen)
                     break;
-                }
-                if (wall_clock64() - t0 > TILE_WAIT_LIMIT) {
-                    __hip_atomic_store(&tc->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
+                // the abort word and the clock only now and then: one load
+                // per poll keeps the release latency down
+                if ((it & 31u) == 0) {
+                    if (__hip_atomic_load(&tc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        ok = 0;
+                        break;
+                    }
+                    if (wall_clock64() - t0 > TILE_WAIT_LIMIT) {
+                        __hip_atomic_store(&tc->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ok = 0;
+                        break;
+                    }
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (fenced)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const unsigned cum = (unsigned)(word >> 32);
+        if (s_quiet)
+            *s_quiet = cum == ts.cchg ? 1 : 0;
+        ts.cchg = cum;
         *s_ok = ok;
     }
     ++ts.gen;
     __syncthreads();
     return *s_ok != 0;
+}
+
+// The exchange copies cross the unfenced epoch barriers: device-scope atomic
+// stores and loads only.
+__device__ __forceinline__ void xs_store(glb_u32* p, uint32_t v)
+{
+    __hip_atomic_store((uint32_t*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t xs_load(const glb_u32* p)
+{
+    return __hip_atomic_load((const uint32_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // What a tile's distance stage reads and writes (global rows and words).
@@ -276,8 +322,8 @@ __device__ __forceinline__ void publish(const Band& b, glb_u32* out)
     const int ntop = top_hi - b.r0;
     auto put = [&](int y, int gw, int sj) {
         const int si = y & 1;
-        out[(size_t)(si * 2 + sj) * b.SUBG + (size_t)(y >> 1) * b.WWg + gw] =
-            g.S[g.sub(si, sj) + ((y - b.e0) >> 1) * WWb + (gw - b.bw0)];
+        xs_store(out + (size_t)(si * 2 + sj) * b.SUBG + (size_t)(y >> 1) * b.WWg + gw,
+                 g.S[g.sub(si, sj) + ((y - b.e0) >> 1) * WWb + (gw - b.bw0)]);
     };
     const int n = (ntop + (b.r1 - bot_lo)) * 2 * nw;
     for (int u = threadIdx.x; u < n; u += TILE_NT) {
@@ -315,7 +361,7 @@ __device__ __forceinline__ void refresh_halo(const Band& b, const glb_u32* in, i
     const int WWb = g.WW;
     auto get = [&](int y, int wb, int sj) {
         const int si = y & 1;
-        const uint32_t nv = in[(size_t)(si * 2 + sj) * b.SUBG + (size_t)(y >> 1) * b.WWg + (b.bw0 + wb)];
+        const uint32_t nv = xs_load(in + (size_t)(si * 2 + sj) * b.SUBG + (size_t)(y >> 1) * b.WWg + (b.bw0 + wb));
         const int rr = (y - b.e0) >> 1;
         const int li = g.sub(si, sj) + rr * WWb + wb;
         if (g.S[li] != nv) {
@@ -366,14 +412,19 @@ __device__ __forceinline__ void refresh_halo(const Band& b, const glb_u32* in, i
 // Levels of one phase in increasing order; in each, epochs of halo / 4
 // rounds and one exchange until a round changed nothing anywhere.
 __device__ __forceinline__ bool tile_levels(Band& b, const TileView& v, TileSync& ts, int* s_ok, int* s_flag,
-                                            lds_u32* cnt, int pi, int nlev, bool thin)
+                                            int* s_quiet, lds_u32* cnt, lds_u32* levf, int pi, int nlev, bool thin)
 {
     Img<true>& g = b.g;
     Sched sc;
     sched_reset(g, sc);
+    // which levels some tile has candidates at (set before the last barrier)
+    for (int q = threadIdx.x; q < nlev; q += TILE_NT)
+        levf[q] = __hip_atomic_load(&ts.tc->lev[pi][q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
+    const bool stats = blockIdx.x == 0 && threadIdx.x == 0;
+    const int epoch_rounds = b.halo >> 2;
     for (int k = 0; k < nlev; ++k) {
-        if (__hip_atomic_load(&ts.tc->lev[pi][k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        if (levf[k] == 0)
             continue;  // no tile has a candidate at this level
         const int ser = ++sc.serial;
         ++ts.acts;
@@ -385,27 +436,27 @@ __device__ __forceinline__ bool tile_levels(Band& b, const TileView& v, TileSync
         }
         __syncthreads();
         const unsigned start = ts.round;
-        unsigned lvl_last = start;  // the level's last round that changed something
+        unsigned lvl_last = start;  // the level's last round that changed something (statistics)
         for (;;) {
-            const int epoch_rounds = b.halo >> 2;
             const int last = run_rounds<true, TILE_NT, true>(g, thin, sc, epoch_rounds, b.lo, b.hi, b.cw0 - b.bw0,
                                                              b.cw1 - b.bw0);
             publish(b, b.Xs[ts.gen & 1]);
-            // by barrier parity: a tile that reads this epoch's word after
-            // the barrier never sees a store of the next epoch (a faster
-            // tile can only store the same word again after the barrier
-            // that the slower one reaches after reading it)
+            // for the round count only, by barrier parity: workgroup 0 reads
+            // this epoch's word after the barrier and before it arrives at
+            // the next one, which no tile passes before it arrives, so no
+            // store of the epoch after the next can have reached the word
             unsigned* lcw = &ts.tc->last_change[ts.gen & 1];
             if (last && threadIdx.x == 0)
                 __hip_atomic_fetch_max(lcw, ts.round + (unsigned)last, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             ts.round += (unsigned)epoch_rounds;
-            if (!tile_sync(ts, s_ok))
+            if (!tile_sync(ts, s_ok, false, last == epoch_rounds, s_quiet))
                 return false;
             // the last round of the epoch changed no tile's own rows: the
             // level is done (the rounds after its first quiet one were no-ops)
-            const unsigned lc = __hip_atomic_load(lcw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const bool done = lc < ts.round;
-            lvl_last = lc > lvl_last ? lc : lvl_last;
+            const bool done = *s_quiet != 0;
+            unsigned lc = 0;
+            if (stats)
+                lc = __hip_atomic_load(lcw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             refresh_halo(b, b.Xs[(ts.gen - 1) & 1], s_flag);
             __syncthreads();
             const int f = *s_flag;
@@ -420,6 +471,7 @@ __device__ __forceinline__ bool tile_levels(Band& b, const TileView& v, TileSync
                     g.ctl[CTL_PROD2 + threadIdx.x] = hs;
                 }
             }
+            lvl_last = lc > lvl_last ? lc : lvl_last;
             if (done) {
                 ts.rounds += (lvl_last - start) + 1u;
                 break;
@@ -430,7 +482,7 @@ __device__ __forceinline__ bool tile_levels(Band& b, const TileView& v, TileSync
 }
 
 __device__ __forceinline__ bool tile_image(const ImgDesc* __restrict__ dp, TileSync& ts, int* s_ok, int* s_flag,
-                                           uint64_t* smem, lds_u32* cnt, lds_i32* ctl, int TH, int ERmax, int halo,
+                                           int* s_quiet, uint64_t* smem, lds_u32* cnt, lds_u32* levf, lds_i32* ctl, int TH, int ERmax, int halo,
                                            int nc, int WWbmax, int nxcd)
 {
     const int H = dp->H, W = dp->W;
@@ -521,7 +573,7 @@ __device__ __forceinline__ bool tile_image(const ImgDesc* __restrict__ dp, TileS
         if (g.hasD)
             Dp[gq] = pack_word(dp->D + (long long)row * ld + 64 * w, n, vec_ok) & ~m;
     }
-    if (!tile_sync(ts, s_ok))
+    if (!tile_sync(ts, s_ok, true))
         return false;
     for (int q = tid; q < b.ER * WWb; q += TILE_NT) {
         const int lr = q / WWb;
@@ -546,7 +598,7 @@ __device__ __forceinline__ bool tile_image(const ImgDesc* __restrict__ dp, TileS
                     Rg[(size_t)(b.e0 + lr) * WW + b.bw0 + wb] =
                         spread_bits(g.S[g.sub(lr & 1, 0) + o]) | (spread_bits(g.S[g.sub(lr & 1, 1) + o]) << 1);
                 }
-                if (!tile_sync(ts, s_ok))
+                if (!tile_sync(ts, s_ok, true))
                     return false;
             }
             clear_candidates(g, tid, TILE_NT);
@@ -558,9 +610,9 @@ __device__ __forceinline__ bool tile_image(const ImgDesc* __restrict__ dp, TileS
             for (int q = tid; q < nlev; q += TILE_NT)
                 if (cnt[q])
                     __hip_atomic_store(&ts.tc->lev[pi][q], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (!tile_sync(ts, s_ok))
+            if (!tile_sync(ts, s_ok, true))
                 return false;
-            if (!tile_levels(b, v, ts, s_ok, s_flag, cnt, pi, nlev, ph == HC_THIN || ph == HF_THIN))
+            if (!tile_levels(b, v, ts, s_ok, s_flag, s_quiet, cnt, levf, pi, nlev, ph == HC_THIN || ph == HF_THIN))
                 return false;
         }
     }
@@ -590,13 +642,14 @@ __global__ __launch_bounds__(TILE_NT) void hasf_tile_kernel(const ImgDesc* __res
 {
     extern __shared__ uint64_t smem[];
     __shared__ unsigned cnt[HASF_LEVELS_MAX];
+    __shared__ unsigned levf[HASF_LEVELS_MAX];
     __shared__ int ctl[CTL_LDS_WORDS];
-    __shared__ int s_ok, s_flag;
+    __shared__ int s_ok, s_flag, s_quiet;
     if (threadIdx.x == 0)
         s_flag = 0;
-    TileSync ts{tc, gridDim.x, 0u, 0u, 0u, 0u};
-    const bool ok =
-        tile_image(dp, ts, &s_ok, &s_flag, smem, (lds_u32*)cnt, (lds_i32*)ctl, TH, ERmax, halo, nc, WWbmax, nxcd);
+    TileSync ts{tc, gridDim.x, 0u, 0u, 0u, 0u, 0u};
+    const bool ok = tile_image(dp, ts, &s_ok, &s_flag, &s_quiet, smem, (lds_u32*)cnt, (lds_u32*)levf, (lds_i32*)ctl,
+                               TH, ERmax, halo, nc, WWbmax, nxcd);
     if (!ok && threadIdx.x == 0) {
         __hip_atomic_store(&tc->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (err_out)
