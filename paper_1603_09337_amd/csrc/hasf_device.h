@@ -594,7 +594,24 @@ __device__ __forceinline__ int run_rounds(const Img<LDS>& g, bool thin, Sched& s
                     changed_own |= c && 2 * rr + si >= ilo && 2 * rr + si < ihi && w >= wlo && w < whi;
                 }
             };
-            if (nw <= 2 * NT) {
+            if (LDS && TILE && nw <= NT) {
+                // one word per thread, tested in place when flagged and live:
+                // no listing, so a pass is one round trip for the flags and
+                // the test (a test writes only its own word of S and flags of
+                // the other three sub-images)
+                // (M and S are loaded with the flag, so the live test waits
+                // for one round trip)
+                const int b = (int)threadIdx.x;
+                if (b < nw) {
+                    const unsigned f = Ds[b];
+                    const uint32_t m = Ms[b], sv = Ss[b];
+                    if (f) {
+                        Ds[b] = 0;
+                        if (m & (sv ^ flip))
+                            test(b);
+                    }
+                }
+            } else if (nw <= 2 * NT) {
                 // one chunk of 128 words per wave, listed at L[w0 ..] and
                 // tested by the same wave: a test writes only its own word of
                 // S and flags of the other three sub-images, and a wave's

@@ -233,3 +233,24 @@ def test_bad_tile_cols_is_refused():
     with pytest.raises(hasf.HasfError) as e:
         hasf.Context(0, tile_cols=-1)
     assert e.value.status == hasf.HASF_EINVAL
+
+
+_FCTX = {}
+
+
+@pytest.mark.parametrize("th", [96, 98, 240])
+def test_tiles_pass_forms_at_their_boundaries(th):
+    # A tile's pass tests one word per thread in place when its sub-image has
+    # at most 1024 words, lists them wave by wave up to 2048, and through one
+    # shared list beyond. W = 1024 (16 words), halo 16, one column tile: bands
+    # of 96 rows keep 128 rows (64 x 16 = 1024 words, in place), of 98 rows
+    # 130 (1040, per wave) and of 240 rows 272 (2176, shared list); the first
+    # band is 16 rows shorter and the last band (H odd) has two sub-image
+    # sizes, so each launch mixes two forms.
+    if th not in _FCTX:
+        _FCTX[th] = hasf.Context(0, grid_min_pixels=1, batch_grid_min_pixels=1, tile_rows=th, tile_halo=16,
+                                 tile_cols=1)
+    X = synth.random_binary(701, 1024, 0.5, 900 + th)
+    C = synth.random_binary(701, 1024, 0.05, 950 + th)
+    say("tile pass forms, tile rows", th)
+    assert np.array_equal(_filter(_FCTX[th], X, C, 3), oracle.hasf(X, C, 3))
