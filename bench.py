@@ -176,9 +176,9 @@ def bench_edt(ctx, reps=20):
 
 
 def bench_large(ctx, reps=3):
-    """The whole filter on the 4096x4096 r=10 image alone (grid path)."""
+    """The whole filter on the 4096x4096 r=10 image alone (the large-image path: tiles in LDS)."""
     import torch
-    from paper_1603_09337_amd import synth
+    from paper_1603_09337_amd import hasf, synth
     X, C, r = synth.workload_large()
     src = torch.from_numpy(X).cuda()
     d = src.clone()
@@ -200,12 +200,11 @@ def bench_large(ctx, reps=3):
     ms = min(ts)
     ms_avg = sum(ts) / len(ts)
     tiled = ctx.tile_rows >= 0
-    # the library's default tile shape for an image of this size (bands of
-    # 128 rows with 32 halo rows from 8 Mpx on, else 64 and 16; the bands cut
-    # into column tiles of whole 64-column words that fill the CUs)
-    large = X.size >= (1 << 23)
-    th = ctx.tile_rows or (128 if large else 64)
-    halo = ctx.tile_halo or (32 if large else 16)
+    # the library's default tile shape for an image of this size (the bands
+    # cut into column tiles of whole 64-column words that fill the CUs)
+    dth, dhalo = hasf.default_tile_shape(*X.shape)
+    th = ctx.tile_rows or dth
+    halo = ctx.tile_halo or dhalo
     out = {"workload": "hasf 4096x4096 r=10, C empty, one image (%s)" %
            ("tiles in LDS: bands of %d rows, %d halo rows, cut into column tiles" % (th, halo) if tiled
             else "grid of workgroups"),

@@ -79,11 +79,12 @@ typedef struct {
                                by tiles of this many own rows (see tile_cols), each tile's state in LDS with
                                tile_halo rows of its neighbours above and below, exchanged every tile_halo / 4
                                rounds;
-                               0 = by image size (HASF_TILE_ROWS_DEFAULT, HASF_TILE_ROWS_LARGE from
-                               HASF_TILE_LARGE_PIXELS on); an even number >= 4 (raised to tile_halo);
+                               0 = by image size (HASF_TILE_ROWS_SMALL below HASF_TILE_SMALL_PIXELS,
+                               HASF_TILE_ROWS_LARGE from HASF_TILE_LARGE_PIXELS on, HASF_TILE_ROWS_DEFAULT
+                               between); an even number >= 4 (raised to tile_halo);
                                -1 = never (the grid of workgroups with the state in global memory) */
-    int tile_halo;          /* 0 = by image size (HASF_TILE_HALO_DEFAULT, HASF_TILE_HALO_LARGE from
-                               HASF_TILE_LARGE_PIXELS on); a multiple of 4 from 4 to 32 */
+    int tile_halo;          /* 0 = by image size (HASF_TILE_HALO_SMALL, HASF_TILE_HALO_DEFAULT or
+                               HASF_TILE_HALO_LARGE, as tile_rows); a multiple of 4 from 4 to 32 */
     const char* tune_cache; /* NULL: lone images are routed by the fields above. Otherwise the path of a text
                                file of measured launch choices (created if missing, read at hasf_create):
                                the first lone image (hasf_filter, hasf_filter_cd, a batch of one) of a size
@@ -100,13 +101,18 @@ typedef struct {
 } hasf_opts;
 
 /* Tile shape by default (measured on MI355X, column tiles filling the CUs):
- * 2048^2 r=8 8.3 ms with 64 rows and 16 halo rows (32 and 12: 9.8 ms); 4096^2
- * r=10 28.0 ms with 128 rows and 32 halo rows (64 and 16: 29.5 ms). */
+ * below HASF_TILE_SMALL_PIXELS 32 rows and 12 halo rows (1400x1300 r=6: 2.97 ms,
+ * 64 and 16: 3.25 ms); up to HASF_TILE_LARGE_PIXELS 64 and 16 (2048^2 r=8:
+ * 6.33 ms, 32 and 12: 6.78 ms); from there on 128 and 24 (4096^2 r=10: 20.5 ms,
+ * 128 and 32: 21.0 ms, 64 and 16: 21.5 ms). */
+#define HASF_TILE_SMALL_PIXELS ((size_t)1 << 21)
+#define HASF_TILE_ROWS_SMALL 32
+#define HASF_TILE_HALO_SMALL 12
 #define HASF_TILE_ROWS_DEFAULT 64
 #define HASF_TILE_HALO_DEFAULT 16
 #define HASF_TILE_LARGE_PIXELS ((size_t)1 << 23)
 #define HASF_TILE_ROWS_LARGE 128
-#define HASF_TILE_HALO_LARGE 32
+#define HASF_TILE_HALO_LARGE 24
 
 /* Create a context on opts->device (opts may be NULL: device 0, defaults).
  * The context owns its scratch memory and the default (null) stream. */

@@ -305,11 +305,12 @@ inline TilePlan tile_plan(int H, int W, int r, size_t lds_cap, int max_tiles, in
     TilePlan P{};
     P.ok = false;
     // the default shape by image size
-    const bool large = (size_t)H * (size_t)W >= HASF_TILE_LARGE_PIXELS;
+    const size_t px = (size_t)H * (size_t)W;
+    const bool large = px >= HASF_TILE_LARGE_PIXELS, small = px < HASF_TILE_SMALL_PIXELS;
     if (halo == 0)
-        halo = large ? HASF_TILE_HALO_LARGE : HASF_TILE_HALO_DEFAULT;
+        halo = large ? HASF_TILE_HALO_LARGE : small ? HASF_TILE_HALO_SMALL : HASF_TILE_HALO_DEFAULT;
     if (TH_req == 0)
-        TH_req = large ? HASF_TILE_ROWS_LARGE : HASF_TILE_ROWS_DEFAULT;
+        TH_req = large ? HASF_TILE_ROWS_LARGE : small ? HASF_TILE_ROWS_SMALL : HASF_TILE_ROWS_DEFAULT;
     if (halo < 4 || halo > 4 * TILE_ROUNDS_MAX_HOST || (halo & 3) || max_tiles < 2)
         return P;
     P.halo = halo;

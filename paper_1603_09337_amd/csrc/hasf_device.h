@@ -517,7 +517,9 @@ __device__ __forceinline__ bool test_word(const PassPtrs<LDS>& p, int idx, int r
 // the list densely; a pass whose sub-image has no flagged word is skipped.
 // A sub-image of at most 2 NT words is instead split into one 128-word chunk
 // per wave, and each wave lists and tests its own chunk's words, which saves
-// the workgroup barrier between listing and testing.
+// the workgroup barrier between listing and testing. In a tile (TILE) a
+// sub-image of at most NT words is tested one word per thread in place, with
+// no list at all.
 // NT: the workgroup size (threads) the caller is launched with.
 //
 // TILE: the state is one tile of a larger image (its own pixels plus halo

@@ -25,6 +25,26 @@ HASF_SERVE_LANES_MAX = 16
 HASF_SERVE_PERSISTENT = 1
 HASF_NOALLOC_SCRATCH_BYTES = 16 << 20
 HASF_INF_COMPOSED = 1
+# the tile shape by image size (as the header's HASF_TILE_* defaults)
+HASF_TILE_SMALL_PIXELS = 1 << 21
+HASF_TILE_ROWS_SMALL = 32
+HASF_TILE_HALO_SMALL = 12
+HASF_TILE_ROWS_DEFAULT = 64
+HASF_TILE_HALO_DEFAULT = 16
+HASF_TILE_LARGE_PIXELS = 1 << 23
+HASF_TILE_ROWS_LARGE = 128
+HASF_TILE_HALO_LARGE = 24
+
+
+def default_tile_shape(H: int, W: int):
+    """(tile rows, halo rows) the library takes for an H x W image when
+    tile_rows and tile_halo are 0."""
+    px = H * W
+    if px >= HASF_TILE_LARGE_PIXELS:
+        return HASF_TILE_ROWS_LARGE, HASF_TILE_HALO_LARGE
+    if px < HASF_TILE_SMALL_PIXELS:
+        return HASF_TILE_ROWS_SMALL, HASF_TILE_HALO_SMALL
+    return HASF_TILE_ROWS_DEFAULT, HASF_TILE_HALO_DEFAULT
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libhasf.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)

@@ -130,3 +130,25 @@ def test_header_is_plain_c_and_links(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stdout + out.stderr
     assert out.stdout.split()[:2] == ["0", "116"]
+
+
+def test_binding_constants_match_the_header():
+    # every HASF_ constant the binding mirrors has the header's value
+    import re
+    hasf, _ = _lib()
+    text = open(os.path.join(ROOT, "include", "libhasf.h")).read()
+    defs = {}
+    for name, expr in re.findall(r"^#define\s+(HASF_\w+)\s+(.+?)\s*(?:/\*.*)?$", text, re.M):
+        expr = expr.replace("(size_t)", "")
+        if re.fullmatch(r"[0-9()<>\s+\-*]+", expr):
+            defs[name] = eval(expr)
+    mirrored = [k for k in dir(hasf) if k.startswith("HASF_") and isinstance(getattr(hasf, k), int)]
+    assert len(mirrored) > 10
+    for k in mirrored:
+        if k in defs:
+            assert getattr(hasf, k) == defs[k], k
+    for k in [k for k in defs if k.startswith("HASF_TILE_")]:
+        assert getattr(hasf, k) == defs[k], k
+    assert hasf.default_tile_shape(4096, 4096) == (defs["HASF_TILE_ROWS_LARGE"], defs["HASF_TILE_HALO_LARGE"])
+    assert hasf.default_tile_shape(2048, 2048) == (defs["HASF_TILE_ROWS_DEFAULT"], defs["HASF_TILE_HALO_DEFAULT"])
+    assert hasf.default_tile_shape(1024, 1024) == (defs["HASF_TILE_ROWS_SMALL"], defs["HASF_TILE_HALO_SMALL"])
