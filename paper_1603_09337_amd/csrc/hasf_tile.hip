@@ -423,59 +423,94 @@ __device__ __forceinline__ bool tile_levels(Band& b, const TileView& v, TileSync
     __syncthreads();
     const bool stats = blockIdx.x == 0 && threadIdx.x == 0;
     const int epoch_rounds = b.halo >> 2;
-    for (int k = 0; k < nlev; ++k) {
-        if (levf[k] == 0)
-            continue;  // no tile has a candidate at this level
+    // the next level after k that some tile has candidates at (uniform)
+    auto next_level = [&](int k) {
+        int kn = k + 1;
+        while (kn < nlev && levf[kn] == 0)
+            ++kn;
+        return __builtin_amdgcn_readfirstlane(kn);
+    };
+    auto entries = [&](int k) {
+        return k < nlev ? (unsigned)__builtin_amdgcn_readfirstlane((int)min(cnt[k], (unsigned)v.slots)) : 0u;
+    };
+    // marks level k's candidates of this tile live; the first entry of each
+    // thread may come in registers (have)
+    auto activate = [&](int k, unsigned c, bool have, uint32_t pi0, uint64_t pm0) {
         const int ser = ++sc.serial;
         ++ts.acts;
-        const unsigned c = min(cnt[k], (unsigned)v.slots);
         const size_t eb = (size_t)k * v.slots;
         for (unsigned u = threadIdx.x; u < c; u += TILE_NT) {
-            const uint32_t p = v.eidx[eb + u];
-            activate_row_word(g, (int)(p >> 10), (int)(p & 1023u), (uint64_t)v.emsk[eb + u], ser);
+            uint32_t p = pi0;
+            uint64_t m = pm0;
+            if (!have || u >= TILE_NT) {
+                p = v.eidx[eb + u];
+                m = (uint64_t)v.emsk[eb + u];
+            }
+            activate_row_word(g, (int)(p >> 10), (int)(p & 1023u), m, ser);
         }
         __syncthreads();
-        const unsigned start = ts.round;
-        unsigned lvl_last = start;  // the level's last round that changed something (statistics)
-        for (;;) {
-            const int last = run_rounds<true, TILE_NT, true>(g, thin, sc, epoch_rounds, b.lo, b.hi, b.cw0 - b.bw0,
-                                                             b.cw1 - b.bw0);
-            publish(b, b.Xs[ts.gen & 1]);
-            // for the round count only, by barrier parity: workgroup 0 reads
-            // this epoch's word after the barrier and before it arrives at
-            // the next one, which no tile passes before it arrives, so no
-            // store of the epoch after the next can have reached the word
-            unsigned* lcw = &ts.tc->last_change[ts.gen & 1];
-            if (last && threadIdx.x == 0)
-                __hip_atomic_fetch_max(lcw, ts.round + (unsigned)last, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ts.round += (unsigned)epoch_rounds;
-            if (!tile_sync(ts, s_ok, false, last == epoch_rounds, s_quiet))
-                return false;
-            // the last round of the epoch changed no tile's own rows: the
-            // level is done (the rounds after its first quiet one were no-ops)
-            const bool done = *s_quiet != 0;
-            unsigned lc = 0;
-            if (stats)
-                lc = __hip_atomic_load(lcw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            refresh_halo(b, b.Xs[(ts.gen - 1) & 1], s_flag);
-            __syncthreads();
-            const int f = *s_flag;
-            __syncthreads();
-            if (f) {
-                // as an activation: both copies of the pass serials
-                const int hs = ++sc.serial;
-                if (threadIdx.x == 0)
-                    *s_flag = 0;
-                if (threadIdx.x < 4) {
-                    g.ctl[CTL_PROD + threadIdx.x] = hs;
-                    g.ctl[CTL_PROD2 + threadIdx.x] = hs;
-                }
+    };
+    int k = next_level(-1);
+    if (k >= nlev)
+        return true;
+    activate(k, entries(k), false, 0u, 0ull);
+    int kn = next_level(k);
+    unsigned cn = entries(kn);
+    unsigned start = ts.round;
+    unsigned lvl_last = start;  // the level's last round that changed something (statistics)
+    for (;;) {
+        const int last = run_rounds<true, TILE_NT, true>(g, thin, sc, epoch_rounds, b.lo, b.hi, b.cw0 - b.bw0,
+                                                         b.cw1 - b.bw0);
+        publish(b, b.Xs[ts.gen & 1]);
+        // for the round count only, by barrier parity: workgroup 0 reads
+        // this epoch's word after the barrier and before it arrives at the
+        // next one, which no tile passes before it arrives, so no store of
+        // the epoch after the next can have reached the word
+        unsigned* lcw = &ts.tc->last_change[ts.gen & 1];
+        if (last && threadIdx.x == 0)
+            __hip_atomic_fetch_max(lcw, ts.round + (unsigned)last, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ts.round += (unsigned)epoch_rounds;
+        if (!tile_sync(ts, s_ok, false, last == epoch_rounds, s_quiet))
+            return false;
+        // the last round of the epoch changed no tile's own rows: the level
+        // is done (the rounds after its first quiet one were no-ops)
+        const bool done = *s_quiet != 0;
+        unsigned lc = 0;
+        if (stats)
+            lc = __hip_atomic_load(lcw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the next level's first entries, loaded with the halo: both are in
+        // flight together, so its activation waits for no load of its own
+        uint32_t pi0 = 0;
+        uint64_t pm0 = 0;
+        if (done && threadIdx.x < cn) {
+            pi0 = v.eidx[(size_t)kn * v.slots + threadIdx.x];
+            pm0 = (uint64_t)v.emsk[(size_t)kn * v.slots + threadIdx.x];
+        }
+        refresh_halo(b, b.Xs[(ts.gen - 1) & 1], s_flag);
+        __syncthreads();
+        const int f = *s_flag;
+        __syncthreads();
+        if (f) {
+            // as an activation: both copies of the pass serials
+            const int hs = ++sc.serial;
+            if (threadIdx.x == 0)
+                *s_flag = 0;
+            if (threadIdx.x < 4) {
+                g.ctl[CTL_PROD + threadIdx.x] = hs;
+                g.ctl[CTL_PROD2 + threadIdx.x] = hs;
             }
-            lvl_last = lc > lvl_last ? lc : lvl_last;
-            if (done) {
-                ts.rounds += (lvl_last - start) + 1u;
+        }
+        lvl_last = lc > lvl_last ? lc : lvl_last;
+        if (done) {
+            ts.rounds += (lvl_last - start) + 1u;
+            if (kn >= nlev)
                 break;
-            }
+            activate(kn, cn, true, pi0, pm0);
+            k = kn;
+            kn = next_level(k);
+            cn = entries(kn);
+            start = ts.round;
+            lvl_last = start;
         }
     }
     return true;
