@@ -570,13 +570,29 @@ __device__ __forceinline__ int run_rounds(const Img<LDS>& g, bool thin, Sched& s
             const lds_i32* prod_rd = g.ctl + CTL_PROD + sc.rd;
             lds_i32* prod = g.ctl + CTL_PROD + (sc.rd ^ 4);
             const int p = prod_rd[s];
+            // in place (TILE, a sub-image of at most NT words): this thread's
+            // flag is loaded with the skip word (and with the four words the
+            // pass carries forward into prod), in one LDS round trip; the
+            // empty asm keeps the compiler from sinking the loads behind the
+            // skip decision. The flag is the one the last executed pass left
+            // behind its barrier.
+            unsigned f1 = 0;
+            int pr = 0;
+            if constexpr (LDS && TILE) {
+                const int nw1 = ((g.H - (s >> 1) + 1) >> 1) * WW;
+                if (nw1 <= NT && (int)threadIdx.x < nw1)
+                    f1 = g.D[g.sub(s >> 1, s & 1) + (int)threadIdx.x];
+                if (threadIdx.x < 4)
+                    pr = prod_rd[threadIdx.x];
+                asm volatile("" ::"v"(f1), "v"(p), "v"(pr));
+            }
             if (p <= sc.consumed[s])
                 continue;  // nothing flagged in this sub-image: the pass would change nothing
             sc.consumed[s] = p;
             const int ser = ++sc.serial;
             if (threadIdx.x < 4)
-                __hip_atomic_fetch_max(prod + threadIdx.x, prod_rd[threadIdx.x], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_max(prod + threadIdx.x, (LDS && TILE) ? pr : prod_rd[threadIdx.x],
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             const int si = s >> 1, sj = s & 1;
             const int so = 1 - si, co = 1 - sj;
             const auto Ss = g.S + g.sub(si, sj);
@@ -597,21 +613,15 @@ __device__ __forceinline__ int run_rounds(const Img<LDS>& g, bool thin, Sched& s
                 }
             };
             if (LDS && TILE && nw <= NT) {
-                // one word per thread, tested in place when flagged and live:
-                // no listing, so a pass is one round trip for the flags and
-                // the test (a test writes only its own word of S and flags of
-                // the other three sub-images)
-                // (M and S are loaded with the flag, so the live test waits
-                // for one round trip)
+                // one word per thread (its flag loaded above), tested in
+                // place when flagged: no listing, so a pass is one round trip
+                // for the skip word and the flags and one for the test (a
+                // test writes only its own word of S and flags of the other
+                // three sub-images)
                 const int b = (int)threadIdx.x;
-                if (b < nw) {
-                    const unsigned f = Ds[b];
-                    const uint32_t m = Ms[b], sv = Ss[b];
-                    if (f) {
-                        Ds[b] = 0;
-                        if (m & (sv ^ flip))
-                            test(b);
-                    }
+                if (b < nw && f1) {
+                    Ds[b] = 0;
+                    test(b);  // loads M and S with the neighbours: no live candidate, no change
                 }
             } else if (nw <= 2 * NT) {
                 // one chunk of 128 words per wave, listed at L[w0 ..] and
