@@ -760,6 +760,10 @@ __device__ __forceinline__ int run_rounds(const Img<LDS>& g, bool thin, Sched& s
         // stored its serial in chg; a round without any pass changes nothing
         if (!TILE && *chg <= round_start)
             break;
+        // TILE: a round that ran no pass leaves prod as it found it, so every
+        // later round of the epoch would skip all its passes too
+        if (TILE && sc.serial == round_start)
+            break;
     }
     // The skip decisions after the last executed pass read prod and chg with
     // no barrier behind them. The caller's next activation writes prod: a

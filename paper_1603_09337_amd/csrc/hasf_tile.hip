@@ -43,7 +43,7 @@ struct TileSync {
     unsigned nblk;
     unsigned gen;     // barriers passed (uniform)
     unsigned round;   // rounds run in this launch (uniform)
-    unsigned rounds;  // rounds of the schedule (thread 0 of workgroup 0)
+    unsigned rounds;  // rounds of the schedule (wave 0 of workgroup 0)
     unsigned acts;    // levels activated (uniform)
     unsigned cchg;    // high half of the barrier word last seen (thread 0)
 };
@@ -359,9 +359,30 @@ __device__ __forceinline__ void refresh_halo(const Band& b, const glb_u32* in, i
 {
     const Img<true>& g = b.g;
     const int WWb = g.WW;
-    auto get = [&](int y, int wb, int sj) {
+    const int ntop = b.r0 - b.e0, nbot = b.e0 + b.ER - b.r1;
+    const int n = (ntop + nbot) * 2 * WWb;  // halo rows over the block words
+    const int hl = b.cw0 - b.bw0, hrr = b.bw0 + WWb - b.cw1;
+    const int ne = hl + hrr;
+    const int m = (b.r1 - b.r0) * 2 * ne;  // halo words over the own rows
+    // item u: its image row y, block word wb and column parity sj
+    auto item = [&](int u, int& y, int& wb, int& sj) {
+        if (u < n) {
+            const int hr = u / (2 * WWb);
+            const int rem = u - hr * 2 * WWb;
+            sj = rem >= WWb ? 1 : 0;
+            wb = rem - sj * WWb;
+            y = hr < ntop ? b.e0 + hr : b.r1 + (hr - ntop);
+        } else {
+            u -= n;  // here ne > 0
+            y = b.r0 + u / (2 * ne);
+            const int rem = u % (2 * ne);
+            sj = rem >= ne ? 1 : 0;
+            const int k = rem - sj * ne;
+            wb = k < hl ? k : (b.cw1 - b.bw0) + (k - hl);
+        }
+    };
+    auto put = [&](int y, int wb, int sj, uint32_t nv) {
         const int si = y & 1;
-        const uint32_t nv = xs_load(in + (size_t)(si * 2 + sj) * b.SUBG + (size_t)(y >> 1) * b.WWg + (b.bw0 + wb));
         const int rr = (y - b.e0) >> 1;
         const int li = g.sub(si, sj) + rr * WWb + wb;
         if (g.S[li] != nv) {
@@ -387,25 +408,29 @@ __device__ __forceinline__ void refresh_halo(const Band& b, const glb_u32* in, i
             *s_flag = 1;
         }
     };
-    const int ntop = b.r0 - b.e0, nbot = b.e0 + b.ER - b.r1;
-    const int n = (ntop + nbot) * 2 * WWb;
-    for (int u = threadIdx.x; u < n; u += TILE_NT) {
-        const int hr = u / (2 * WWb);
-        const int rem = u - hr * 2 * WWb;
-        const int sj = rem >= WWb ? 1 : 0;
-        get(hr < ntop ? b.e0 + hr : b.r1 + (hr - ntop), rem - sj * WWb, sj);
-    }
-    const int hl = b.cw0 - b.bw0, hrr = b.bw0 + WWb - b.cw1;
-    const int ne = hl + hrr;
-    if (ne == 0)
-        return;
-    const int m = (b.r1 - b.r0) * 2 * ne;
-    for (int u = threadIdx.x; u < m; u += TILE_NT) {
-        const int y = b.r0 + u / (2 * ne);
-        const int rem = u % (2 * ne);
-        const int sj = rem >= ne ? 1 : 0;
-        const int k = rem - sj * ne;
-        get(y, k < hl ? k : (b.cw1 - b.bw0) + (k - hl), sj);
+    // K items per thread and batch: their loads are all in flight before
+    // the first is compared, one memory round trip per batch
+    constexpr int K = 2;
+    const int T = n + m;
+    for (int base = 0; base < T; base += K * TILE_NT) {
+        uint32_t nv[K];
+        int yy[K], ww[K], ss[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int u = base + k * TILE_NT + (int)threadIdx.x;
+            yy[k] = -1;
+            ww[k] = ss[k] = 0;
+            nv[k] = 0;
+            if (u < T) {
+                item(u, yy[k], ww[k], ss[k]);
+                nv[k] = xs_load(in + (size_t)((yy[k] & 1) * 2 + ss[k]) * b.SUBG + (size_t)(yy[k] >> 1) * b.WWg +
+                                (b.bw0 + ww[k]));
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (yy[k] >= 0)
+                put(yy[k], ww[k], ss[k], nv[k]);
     }
 }
 
@@ -421,7 +446,9 @@ __device__ __forceinline__ bool tile_levels(Band& b, const TileView& v, TileSync
     for (int q = threadIdx.x; q < nlev; q += TILE_NT)
         levf[q] = __hip_atomic_load(&ts.tc->lev[pi][q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    const bool stats = blockIdx.x == 0 && threadIdx.x == 0;
+    // the round statistics: all of wave 0 of workgroup 0 (a wave-uniform branch,
+    // so the load of the change word is not waited for where it is issued)
+    const bool stats = blockIdx.x == 0 && threadIdx.x < 64;
     const int epoch_rounds = b.halo >> 2;
     // the next level after k that some tile has candidates at (uniform)
     auto next_level = [&](int k) {
@@ -500,6 +527,9 @@ __device__ __forceinline__ bool tile_levels(Band& b, const TileView& v, TileSync
                 g.ctl[CTL_PROD2 + threadIdx.x] = hs;
             }
         }
+        // (the empty asm keeps the compiler from moving this maximum, and with
+        // it the wait for lc, up to the load)
+        asm volatile("" : "+v"(lc));
         lvl_last = lc > lvl_last ? lc : lvl_last;
         if (done) {
             ts.rounds += (lvl_last - start) + 1u;
