@@ -506,12 +506,13 @@ def _oracle_share(args):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(Xs, Cs, n, distinct):
+def cpu_baseline(Xs, Cs, n, distinct, max_cores=16, per=3):
     """The oracle (plain C, one thread per process, as it stands) on n of the
-    512x512 r=5 images on one core, then on up to 16 host cores as
-    independent processes with 3 images each (images are independent)."""
+    512x512 r=5 images on one core, then on up to max_cores host cores as
+    independent processes with `per` images each (images are independent)."""
     import multiprocessing as mp
     import oracle
+    from paper_1603_09337_amd import synth
     log("cpu oracle: %d frames on one core" % n)
     t0 = time.perf_counter()
     for k in range(n):
@@ -522,8 +523,7 @@ def cpu_baseline(Xs, Cs, n, distinct):
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
         avail = os.cpu_count() or 1
-    cores = max(1, min(16, avail))
-    per = 3
+    cores = max(1, min(max_cores, avail))
     shares = [([Xs[(c * per + j) % distinct] for j in range(per)], [Cs[(c * per + j) % distinct] for j in range(per)])
               for c in range(cores)]
     log("cpu oracle: %d frames on %d processes" % (cores * per, cores))
@@ -540,8 +540,7 @@ def cpu_baseline(Xs, Cs, n, distinct):
     t6 = time.perf_counter()
     oracle.wshed(Gw)
     t7 = time.perf_counter()
-        # the 3D oracle on one volume of the 3D leg's workload, one core
-    from paper_1603_09337_amd import synth
+    # the 3D oracle on one volume of the 3D leg's workload, one core
     vols, r3 = synth.workload_volumes(n=1)
     log("cpu oracle: one 64^3 volume, r=3")
     t4 = time.perf_counter()
