@@ -645,29 +645,32 @@ __device__ __forceinline__ int run_rounds(const Img<LDS>& g, bool thin, Sched& s
                     m2 = *(U2)(Ms + b0);
                     s2 = *(U2)(Ss + b0);
                 }
-                unsigned nl = 0;
-                int q0 = 0, q1 = 0;
-                if (f2) {
-                    *(F2)(Ds + b0) = (uint16_t)0;
-                    if ((f2 & 0xFFu) && (m2.x & (s2.x ^ flip))) {
-                        q0 = b0;
-                        nl = 1;
+                // a wave none of whose 128 words is flagged lists nothing
+                if (__ballot(f2 != 0u) != 0) {
+                    unsigned nl = 0;
+                    int q0 = 0, q1 = 0;
+                    if (f2) {
+                        *(F2)(Ds + b0) = (uint16_t)0;
+                        if ((f2 & 0xFFu) && (m2.x & (s2.x ^ flip))) {
+                            q0 = b0;
+                            nl = 1;
+                        }
+                        if ((f2 >> 8) && b0 + 1 < nw && (m2.y & (s2.y ^ flip))) {
+                            if (nl) q1 = b0 + 1;
+                            else q0 = b0 + 1;
+                            ++nl;
+                        }
                     }
-                    if ((f2 >> 8) && b0 + 1 < nw && (m2.y & (s2.y ^ flip))) {
-                        if (nl) q1 = b0 + 1;
-                        else q0 = b0 + 1;
-                        ++nl;
+                    unsigned tot;
+                    const unsigned off = wave_prefix(nl, &tot);
+                    if (tot) {
+                        const auto Lw = g.L + w0;
+                        if (nl > 0) Lw[off] = q0;
+                        if (nl > 1) Lw[off + 1] = q1;
+                        wave_sync();
+                        for (int t = lane; t < (int)tot; t += 64)
+                            test((int)Lw[t]);
                     }
-                }
-                unsigned tot;
-                const unsigned off = wave_prefix(nl, &tot);
-                if (tot) {
-                    const auto Lw = g.L + w0;
-                    if (nl > 0) Lw[off] = q0;
-                    if (nl > 1) Lw[off + 1] = q1;
-                    wave_sync();
-                    for (int t = lane; t < (int)tot; t += 64)
-                        test((int)Lw[t]);
                 }
             } else {
                 lds_i32* cnt = lcnt + (sc.npass & 1);
@@ -688,6 +691,9 @@ __device__ __forceinline__ int run_rounds(const Img<LDS>& g, bool thin, Sched& s
                         m4 = *(U4)(Ms + b0);
                         s4 = *(U4)(Ss + b0);
                     }
+                    // a wave none of whose 256 words is flagged lists nothing
+                    if (__ballot(f4 != 0u) == 0)
+                        continue;
                     // bit j of keep: word b0 + j is flagged, inside the
                     // sub-image and has live candidates
                     const int rem = nw - b0;
