@@ -35,6 +35,13 @@
 //                 off the hull by bisection and a forward walk. Its cost
 //                 does not depend on the distances; the frame is applied
 //                 as a minimum at the end, so sparse rows keep small hulls.
+//                 g is finite exactly in the columns that hold a feature
+//                 somewhere, so every row has the same such columns
+//                 (edt_colcarry marks and counts them); when there are at
+//                 most ENV_FEW, edt_rows32 leaves every row to edt_rows_env
+//                 unread, and each row takes the minimum over them directly
+//                 (each thread a run of consecutive pixels, whose lowest
+//                 column only moves right).
 //
 // HBM traffic: 1 B/px read + 4 B/px written, plus 3/8 B/px of masks and
 // carries; the per-column g never leaves LDS. With no feature at all (and no
@@ -63,6 +70,34 @@ constexpr int ENV_AVG = 16;
 constexpr int ENV_CAP = 1024;
 constexpr int ENV_NT = 256;       // threads of an edt_rows_env workgroup (one row at a time)
 constexpr int ENV_W_MAX = 16384;  // widest row edt_rows_env takes (its LDS: about 8 bytes per column)
+// an image with at most this many columns that hold a feature: edt_rows_env
+// takes the minimum over those columns directly
+constexpr int ENV_FEW = 32;
+// the columns with a feature are counted in FC_PARTS counters (a workgroup
+// of edt_colcarry adds to counter blockIdx.x % FC_PARTS), FC_STRIDE ints
+// apart, so that few atomics queue on each, and FC_BASE ints after the count
+// of listed strips, so that reading them does not slow the listing's
+// atomics (measured: with the counters in the strip count's 512 bytes, the
+// listing of 2048 strips took 40 us longer)
+constexpr int FC_PARTS = 8;
+constexpr int FC_STRIDE = 16;
+constexpr int FC_BASE = 1024;
+constexpr int CTL_INTS = FC_BASE + FC_STRIDE * FC_PARTS;  // the strip count and the counters
+
+__device__ __forceinline__ int fc_index(int x)  // counter x = 0 .. FC_PARTS - 1
+{
+    return FC_BASE + x * FC_STRIDE;
+}
+
+__device__ __forceinline__ int feature_columns(const int* __restrict__ ctl)
+{
+    int n = 0;
+#pragma unroll
+    for (int x = 0; x < FC_PARTS; ++x)
+        n += ctl[fc_index(x)];
+    return n;
+}
+static_assert(ENV_FEW <= 64, "the feature columns are sorted and evaluated by one wave");
 
 // one thread per 4 columns and 32-row segment: the segment's features as masks
 __global__ __launch_bounds__(256) void edt_colmask(const uint8_t* __restrict__ F, long long ld, int H, int W,
@@ -71,9 +106,10 @@ __global__ __launch_bounds__(256) void edt_colmask(const uint8_t* __restrict__ F
 {
     const int c4 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
     const int s = blockIdx.y;
-    // the list of strips for edt_rows_env starts empty (this kernel runs first)
-    if (hard_count && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
-        *hard_count = 0;
+    // the list of strips for edt_rows_env and the count of columns with a
+    // feature start empty (this kernel runs first)
+    if (hard_count && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x <= FC_PARTS)
+        hard_count[threadIdx.x == 0 ? 0 : fc_index((int)threadIdx.x - 1)] = 0;
     if (c4 >= W)
         return;
     const int r0 = s * SEG;
@@ -110,11 +146,37 @@ __global__ __launch_bounds__(256) void edt_colmask(const uint8_t* __restrict__ F
 // (above, -1 if none) and below it (below, NO_ROW_BELOW if none). A block
 // covers CARRY_COLS columns; the CARRY_GROUPS threads of a column split its
 // segments into consecutive groups, scan them, and combine through LDS.
+//
+// fcb, fcn (may be NULL): bit l of fcb[blockIdx.x] says whether column
+// blockIdx.x * CARRY_COLS + l holds a feature, and the counters of fcn
+// (see feature_columns) count such columns (stores and an atomic that
+// nothing waits for).
+__device__ __forceinline__ void note_feature_columns(const int (*glast)[CARRY_COLS], int c, int W,
+                                                     uint16_t* __restrict__ fcb, int* __restrict__ fcn)
+{
+    // called by all of wave 0; lanes 0 .. CARRY_COLS - 1 stand for the
+    // workgroup's columns (c is lane lc's column)
+    const int lc = threadIdx.x;
+    bool has = false;
+    if (lc < CARRY_COLS && c < W)
+        for (int k = 0; k < CARRY_GROUPS; ++k)
+            has |= glast[k][lc] >= 0;
+    const uint64_t bal = __ballot(has);
+    if (lc == 0) {
+        fcb[blockIdx.x] = (uint16_t)bal;
+        if (bal)
+            atomicAdd(fcn + fc_index(blockIdx.x % FC_PARTS), (int)__popcll(bal));
+    }
+}
+
 __global__ __launch_bounds__(CARRY_COLS* CARRY_GROUPS) void edt_colcarry(const uint32_t* __restrict__ mask,
                                                                          int nseg, int W,
                                                                          int* __restrict__ above,
-                                                                         int* __restrict__ below)
+                                                                         int* __restrict__ below,
+                                                                         uint16_t* __restrict__ fcb,
+                                                                         int* __restrict__ fcn)
 {
+    static_assert(CARRY_COLS <= 16, "one 16-bit word of feature columns per workgroup");
     __shared__ int glast[CARRY_GROUPS][CARRY_COLS], gfirst[CARRY_GROUPS][CARRY_COLS];
     const int lc = threadIdx.x % CARRY_COLS, grp = threadIdx.x / CARRY_COLS;
     const int c = blockIdx.x * CARRY_COLS + lc;
@@ -138,6 +200,8 @@ __global__ __launch_bounds__(CARRY_COLS* CARRY_GROUPS) void edt_colcarry(const u
         glast[grp][lc] = last;
         gfirst[grp][lc] = first;
         __syncthreads();
+        if (fcb && threadIdx.x < 64)
+            note_feature_columns(glast, c, W, fcb, fcn);
         if (c >= W)
             return;
         int up = -1, dn = NO_ROW_BELOW;
@@ -177,6 +241,8 @@ __global__ __launch_bounds__(CARRY_COLS* CARRY_GROUPS) void edt_colcarry(const u
     glast[grp][lc] = last;
     gfirst[grp][lc] = first;
     __syncthreads();
+    if (fcb && threadIdx.x < 64)
+        note_feature_columns(glast, c, W, fcb, fcn);
     if (c >= W)
         return;
     int up = -1, dn = NO_ROW_BELOW;
@@ -351,6 +417,11 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
     const int r0 = strip_id * STRIP;
     if (r0 >= H)
         return;
+    // few columns with a feature (counted by edt_colcarry): edt_rows_env
+    // takes every row and this strip only computes its columns
+    const bool few_test = hard_list && W > 2 * ENV_FEW;
+    // every wave reads the counters (counter lane % FC_PARTS per lane)
+    const int part = few_test ? hard_count[fc_index(threadIdx.x & (FC_PARTS - 1))] : 0;
     const int nr = min(STRIP, H - r0);
     const int s = r0 / SEG;
     const uint32_t pad = frame ? 0u : G2_INF;
@@ -363,11 +434,8 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
         s_cost = 0;
     int has = 0;
     uint32_t cost = 0;
-#pragma unroll 4
-    for (int c = threadIdx.x; c < W; c += blockDim.x) {
-        const uint32_t m = mask[(size_t)s * W + c];
-        const int up0 = above[(size_t)s * W + c];
-        const int dn0 = below[(size_t)s * W + c];
+    // one column: its g^2 in the strip's rows (into LDS) and its cost
+    auto column = [&](int c, uint32_t m, int up0, int dn0) {
         has |= (m != 0) | (up0 >= 0) | (dn0 != NO_ROW_BELOW);
         // nearest feature row above the strip (at or before r0 - 1) and below
         // it (at or after r0 + nr), then running values down and up the strip;
@@ -401,6 +469,20 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
             cost += (uint32_t)min(g, ENV_CAP);
             g2s[r * WP + PAD + c] = g2;
         }
+    };
+#pragma unroll 4
+    for (int c = threadIdx.x; c < W; c += blockDim.x)
+        column(c, mask[(size_t)s * W + c], above[(size_t)s * W + c], below[(size_t)s * W + c]);
+    // few columns with a feature: edt_rows_env takes every row (the test
+    // comes after the column loop, where the counters' load has long
+    // arrived, so that a strip with work does not wait for it)
+    {
+        int nfc = part;
+#pragma unroll
+        for (int o = 1; o < FC_PARTS; o <<= 1)
+            nfc += __shfl_xor(nfc, o);
+        if (few_test && nfc <= ENV_FEW)
+            return;  // uniform
     }
     const int any = __syncthreads_or(has);
     if (!frame && !any) {
@@ -583,13 +665,18 @@ __global__ __launch_bounds__(ENV_NT) void edt_rows_env(const uint32_t* __restric
                                                        const int* __restrict__ above,
                                                        const int* __restrict__ below, int H, int W, int frame,
                                                        int strip, const int* __restrict__ hard_count,
-                                                       const int* __restrict__ hard_list, uint32_t* __restrict__ d2,
+                                                       const int* __restrict__ hard_list,
+                                                       const uint16_t* __restrict__ fcb, uint32_t* __restrict__ d2,
                                                        long long ldo)
 {
     extern __shared__ uint32_t env_sm[];
     // (short: with 4 bytes each, four workgroups would not fit a CU at W = 4096)
     __shared__ short st[ENV_NT], en[ENV_NT], prv[ENV_NT], nxt[ENV_NT], gfirst[ENV_NT], glast[ENV_NT];
     __shared__ int s_wave[2][ENV_NT / 64];
+    // the image's columns with a feature in increasing order when there are
+    // at most ENV_FEW, and their g^2 in the current row
+    __shared__ int fc_k[ENV_FEW];
+    __shared__ uint32_t fc_g2[ENV_FEW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lb = 31 - __clz((unsigned)((W + ENV_NT - 1) / ENV_NT * 2 - 1));  // B = 2^lb
     const int B = 1 << lb;
@@ -598,14 +685,126 @@ __global__ __launch_bounds__(ENV_NT) void edt_rows_env(const uint32_t* __restric
     uint32_t* band = env_sm + tid * S;
     uint32_t* hull = env_sm + ENV_NT * S;
     const int c0 = min(W, tid * B), nb = min(W, c0 + B) - c0;
-    const int nrows = *hard_count * strip;
+    // few columns with a feature (W > 2 ENV_FEW): every row, which
+    // edt_rows32 left unread; else the rows of the listed strips
+    const int nfc = feature_columns(hard_count);
+    const bool all_rows = W > 2 * ENV_FEW && nfc <= ENV_FEW;
+    const int nrows = all_rows ? H : hard_count[0] * strip;
+    if (nrows == 0)
+        return;
+    // the columns with a feature (edt_colcarry's bits and count), in
+    // increasing order when there are few: thread t takes Q consecutive bit
+    // words and places its columns after those of the threads before it
+    if (nfc <= ENV_FEW) {
+        const int nwd = (W + 15) / 16, Q = (nwd + ENV_NT - 1) / ENV_NT;
+        int cnt = 0;
+        for (int q = 0; q < Q; ++q) {
+            const int w = tid * Q + q;
+            cnt += w < nwd ? __popc((uint32_t)fcb[w]) : 0;
+        }
+        int pre = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(pre, o);
+            if (lane >= o)
+                pre += v;
+        }
+        if (lane == 63)
+            s_wave[0][wave] = pre;
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < ENV_NT / 64; ++w)
+            pre += w < wave ? s_wave[0][w] : 0;
+        pre -= cnt;
+        for (int q = 0; q < Q && cnt; ++q) {
+            const int w = tid * Q + q;
+            uint32_t bits = w < nwd ? (uint32_t)fcb[w] : 0u;
+            while (bits) {
+                const int l = __ffs(bits) - 1;
+                bits &= bits - 1u;
+                fc_k[pre++] = w * 16 + l;
+            }
+        }
+        __syncthreads();
+    }
+    // few: each thread's run of B consecutive pixels (B: the band width,
+    // B * ENV_NT >= W), staged at j + j / B so that the threads' runs start
+    // in different banks; (j - k)^2 + g^2 < 2^32 with 24-bit multiplies
+    // (|j - k| and g below 2^16)
+    const int j0 = min(W, tid * B), j1 = min(W, j0 + B);
+    auto few_f = [&](int q, int j) {
+        const int k = fc_k[q];
+        const uint32_t d = (uint32_t)(j > k ? j - k : k - j);
+        return __umul24(d, d) + fc_g2[q];
+    };
     for (int b = blockIdx.x; b < nrows; b += gridDim.x) {
-        const int i = hard_list[b / strip] * strip + b % strip;
+        const int i = all_rows ? b : hard_list[b / strip] * strip + b % strip;
         if (i >= H)
             continue;  // uniform: a strip's rows past the image
         const int s = i / SEG;
         const int bi = i - s * SEG;
         const size_t base = (size_t)s * W;
+        if (nfc <= ENV_FEW) {
+            if (tid < nfc) {
+                const int c = fc_k[tid];
+                const uint32_t m = mask[base + c];
+                const uint32_t lo = m & (0xFFFFFFFFu >> (31 - bi));
+                const uint32_t hi = m >> bi;
+                const int up = lo ? s * SEG + 31 - __clz(lo) : above[base + c];
+                const int dn = hi ? i + __ffs(hi) - 1 : below[base + c];
+                int v = NO_ROW_BELOW;
+                if (up >= 0)
+                    v = i - up;
+                if (dn != NO_ROW_BELOW)
+                    v = min(v, dn - i);
+                fc_g2[tid] = __umul24((uint32_t)v, (uint32_t)v);  // finite: the column holds a feature
+            }
+            __syncthreads();
+            uint32_t* out = d2 + (long long)i * ldo;
+            const uint32_t fv = frame ? (uint32_t)min(i + 1, H - i) * (uint32_t)min(i + 1, H - i) : G2_INF;
+            if (j0 < j1) {
+                // the first column (in increasing order) that is lowest at
+                // the run's first and last pixels: lowest columns only move
+                // right as j grows (two parabolas of equal width cross
+                // once), so at every pixel of the run a lowest column lies
+                // between them
+                int qa = 0, qb = 0;
+                uint32_t va = G2_INF, vb = G2_INF;
+                for (int q = 0; q < nfc; ++q) {
+                    const uint32_t fa = few_f(q, j0), fb = few_f(q, j1 - 1);
+                    if (fa < va) {
+                        va = fa;
+                        qa = q;
+                    }
+                    if (fb < vb) {
+                        vb = fb;
+                        qb = q;
+                    }
+                }
+                for (int j = j0; j < j1; ++j) {
+                    uint32_t v = G2_INF;
+                    for (int q = qa; q <= qb && q < nfc; ++q)
+                        v = min(v, few_f(q, j));
+                    env_sm[j + (j >> lb)] = v;  // staged, then written coalesced
+                }
+            }
+            __syncthreads();
+            // the row is written from a rotated start (whole 64-column
+            // chunks), so that the workgroups writing rows at the same time
+            // are not all at the same offsets of their rows
+            const int rot = (int)(((unsigned)i * 37u) % (unsigned)((W + 63) / 64)) * 64;
+            for (int jj = tid; jj < W; jj += ENV_NT) {
+                const int j = jj + rot < W ? jj + rot : jj + rot - W;
+                uint32_t v = env_sm[j + (j >> lb)];
+                if (frame) {
+                    const uint32_t e = (uint32_t)min(j + 1, W - j);
+                    v = min(v, min(fv, __umul24(e, e)));
+                }
+                out[j] = v;
+            }
+            __syncthreads();  // the next row rewrites the columns' values and the staging
+            continue;
+        }
 #pragma unroll 8
         for (int c = tid; c < W; c += ENV_NT) {
             const uint32_t m = mask[base + c];
@@ -756,7 +955,10 @@ size_t edt_scratch_bytes(int H, int W)
 {
     const size_t nseg = (size_t)(H + SEG - 1) / SEG;
     // masks, carries above and below; the count and list of strips for edt_rows_env
-    return nseg * W * (sizeof(uint32_t) + 2 * sizeof(int)) + 3 * 256 + 256 + (size_t)H * sizeof(int) + 256;
+    // and the feature columns' bits (one uint16 per 16 columns)
+    return nseg * W * (sizeof(uint32_t) + 2 * sizeof(int)) + 3 * 256 + CTL_INTS * sizeof(int) +
+           ((size_t)H * sizeof(int) + 255) / 256 * 256 +
+           ((size_t)(W + 15) / 16 * sizeof(uint16_t) + 255) / 256 * 256;
 }
 
 // scratch: device memory of edt_scratch_bytes(H, W)
@@ -774,8 +976,10 @@ hipError_t launch_edt(const uint8_t* F, int H, int W, long long ld, int frame, i
     int* below = (int*)p;
     p += ((size_t)nseg * W * sizeof(int) + 255) / 256 * 256;
     int* hard_count = (int*)p;
-    p += 256;
+    p += CTL_INTS * sizeof(int);
     int* hard_list = (int*)p;  // at most one entry per row
+    p += ((size_t)H * sizeof(int) + 255) / 256 * 256;
+    uint16_t* fcb = (uint16_t*)p;  // counted by the counters after hard_count[0]
     // rows up to ENV_W_MAX wide that edt_rows32 takes get the envelope for far strips
     const bool env = W <= ENV_W_MAX;
 
@@ -783,7 +987,7 @@ hipError_t launch_edt(const uint8_t* F, int H, int W, long long ld, int frame, i
     hipLaunchKernelGGL(edt_colmask, dim3((W + 1023) / 1024, nseg), dim3(256), 0, stream, F, ld, H, W, invert, vec4,
                        mask, env ? hard_count : nullptr);
     hipLaunchKernelGGL(edt_colcarry, dim3((W + CARRY_COLS - 1) / CARRY_COLS), dim3(CARRY_COLS * CARRY_GROUPS), 0,
-                       stream, mask, nseg, W, above, below);
+                       stream, mask, nseg, W, above, below, env ? fcb : nullptr, env ? hard_count : nullptr);
     // strip height: a divisor of 32 (a strip lies in one segment), as LDS
     // allows (1 KiB is left for the kernels' static LDS): up to 4 rows of
     // padded uint32 g^2 in half the LDS (two workgroups per CU), else in all
@@ -841,7 +1045,7 @@ hipError_t launch_edt(const uint8_t* F, int H, int W, long long ld, int frame, i
             // workgroups also keep the launch cheap when nothing was listed
             const int egrid = std::max(1, std::min(rows, 1024));
             hipLaunchKernelGGL(edt_rows_env, dim3(egrid), dim3(ENV_NT), row_lds, stream, mask, above, below, H, W,
-                               frame, strip, hard_count, hard_list, d2, ldo);
+                               frame, strip, hard_count, hard_list, fcb, d2, ldo);
         }
         return hipGetLastError();
     }

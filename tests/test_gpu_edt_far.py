@@ -1,9 +1,10 @@
 """Parity of the exact squared EDT on inputs whose features are far from most
 pixels: few features, empty columns, features only at one edge, with and
 without the frame. These strips go to the envelope row pass (the windowed
-search would cost each pixel about its distance to the nearest feature);
-the rest of the image keeps the windowed search, so images that mix both are
-checked too. Bit-exact against the oracle's transform; the sparse 4096^2
+search would cost each pixel about its distance to the nearest feature), and
+images whose features lie in at most 32 columns to its direct minimum over
+those columns (both sides of that threshold are checked); the rest of the
+image keeps the windowed search, so images that mix both are checked too. Bit-exact against the oracle's transform; the sparse 4096^2
 case is also timed against the dense workload."""
 import numpy as np
 import pytest
@@ -38,6 +39,20 @@ def test_edt_sparse(shape, frame):
         F = _sparse(H, W, n, H * 7 + W + n)
         say("edt sparse", shape, n, "frame" if frame else "")
         assert np.array_equal(_edt(F, frame), oracle.edt_sq(F, frame)), (shape, n)
+
+
+@pytest.mark.parametrize("ncols", [31, 32, 33, 64])
+@pytest.mark.parametrize("frame", [False, True])
+def test_edt_rows_with_few_feature_columns(ncols, frame):
+    # every row of a far strip has exactly ncols columns with a feature: up to
+    # 32 the row takes the direct minimum over them, beyond it the envelope
+    rng = np.random.default_rng(600 + ncols)
+    F = np.zeros((600, 2000), np.uint8)
+    cols = rng.choice(2000, ncols, replace=False)
+    F[rng.integers(0, 600, ncols), cols] = 1
+    F[rng.integers(0, 600, ncols), cols] = 1  # a second feature in some columns
+    say("edt few feature columns", ncols, "frame" if frame else "")
+    assert np.array_equal(_edt(F, frame), oracle.edt_sq(F, frame))
 
 
 @pytest.mark.parametrize("frame", [False, True])
@@ -98,8 +113,9 @@ def test_edt_sparse_4096_parity_and_timing():
 
     dense, sparse, sparse_f = t(xd, True), t(sd, False), t(sd, True)
     say("edt 4096^2 ms: dense %.4f, sparse %.4f, sparse with frame %.4f" % (dense, sparse, sparse_f))
-    # the far strips take the envelope pass, linear in the row length: a
-    # sparse image costs a small multiple of the dense one (about 3x on
-    # MI355X), not the sum of its pixels' distances (thousands of times the
-    # dense cost); the bound leaves room for a busy device
-    assert sparse < 6 * dense and sparse_f < 6 * dense
+    # 16 features lie in at most 16 columns: every row takes the direct
+    # minimum over those columns, linear in the row length, so the sparse
+    # image costs less than twice the dense one on MI355X (not the sum of
+    # its pixels' distances, thousands of times the dense cost); the bound
+    # leaves room for a busy device
+    assert sparse < 4 * dense and sparse_f < 4 * dense
