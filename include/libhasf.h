@@ -183,8 +183,9 @@ hasf_status hasf_edt_sq(hasf_ctx* ctx, const uint8_t* feat, int H, int W, int64_
  * the same transform, the same kernels and the same arguments and results,
  * but it calls no hipMalloc, hipFree or other allocating routine. Its
  * scratch (per 32-row segment and column: a feature mask and the nearest
- * feature rows above and below; a list of row strips; in all
- * ceil(H / 32) * W * 12 + 4 H + 1280 bytes) lives in
+ * feature rows above and below; a list of row strips; marks and counters of
+ * the columns that hold a feature; in all at most
+ * ceil(H / 32) * W * 12 + 4 H + W / 8 + 6144 bytes) lives in
  * a device array of HASF_NOALLOC_SCRATCH_BYTES that the library holds on
  * each device it runs on until the process ends; 4096 x 4096 needs 6 MiB.
  * HASF_EINVAL (nothing enqueued) for the arguments hasf_edt_sq rejects and
