@@ -53,7 +53,7 @@ def test_noalloc_at_4096_and_sparse_features():
 def test_noalloc_rejects_sizes_beyond_its_scratch():
     lib = hasf.lib()
     p = ctypes.c_void_p(0x1000)
-    # ceil(H / 32) * W * 12 + 4 H + 1280 bytes of scratch: 8192 x 8192 needs 24 MiB
+    # at most ceil(H / 32) * W * 12 + 4 H + W / 8 + 6144 bytes of scratch: 8192 x 8192 needs 24 MiB
     st = lib.hasf_edt_sq_noalloc(ctx()._h, p, 8192, 8192, 8192, 0, p, 8192)
     assert st == hasf.HASF_EINVAL
     assert b"HASF_NOALLOC_SCRATCH_BYTES" in lib.hasf_last_error(ctx()._h)
