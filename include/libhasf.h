@@ -262,7 +262,7 @@ hasf_status hasf_filter_cd(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, const ui
  * leave X unchanged, or after radius r_max (r_max = 0: the saturation radius,
  * the least i with i^2 >= (H-1)^2 + (W-1)^2, from which on every radius
  * applies the same operator); *r_used would receive the last radius applied.
- * SWITCHED OFF in this build: after validating its arguments (HASF_EINVAL as
+ * SWITCHED OFF in this version: after validating its arguments (HASF_EINVAL as
  * hasf_filter_cd, r_used == NULL, r_max < 0, flags other than 0 or
  * HASF_INF_COMPOSED) it returns HASF_EINTERNAL with *r_used = 0 and does no
  * device work.

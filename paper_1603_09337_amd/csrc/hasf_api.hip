@@ -1180,7 +1180,7 @@ hasf_status hasf_filter_inf(hasf_ctx* ctx, uint8_t* X, const uint8_t* C, const u
     // radius per launch, with byte-plane kernels for the constraint sets and
     // the change test) ended in a device memory fault whose cause is not
     // found. The oracle's definition stays; no device work is done here.
-    set_err(ctx, "%s: switched off (r = infinity is not run on the device in this build)", what);
+    set_err(ctx, "%s: switched off (r = infinity is not run on the device in this version)", what);
     return HASF_EINTERNAL;
 }
 
