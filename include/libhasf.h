@@ -393,6 +393,7 @@ hasf_status hasf_filter_labels(hasf_ctx* ctx, const uint8_t* L, int H, int W, in
  * Frames are device-resident: img->X (and img->C) are DEVICE pointers, filtered
  * in place; the caller keeps them alive and untouched until the frame's
  * hasf_serve_wait has returned. Frames must not overlap one another.
+ * hasf_serve_submit_host takes a frame in host memory instead.
  */
 #define HASF_SERVE_LANES_MAX 16
 /* opts.flags bit: the persistent polling kernel (workgroups that stay resident
@@ -440,6 +441,18 @@ hasf_status hasf_serve(hasf_ctx* ctx, const hasf_serve_opts* opts, hasf_server**
 /* Thread-safe. Validates the frame (HASF_EINVAL, nothing queued), then queues
  * it; HASF_EAGAIN when max_pending frames are already waiting. */
 hasf_status hasf_serve_submit(hasf_server* s, const hasf_image* img, uint64_t* ticket);
+/* The same for a frame in HOST memory: img->X (in/out), img->C and img->D
+ * (or NULL) are host pointers (H rows of ld bytes). When the frame is admitted
+ * the dispatcher enqueues copies of them into the frame's block of the device
+ * pool (which is sized for them too: the scratch plus H W bytes per buffer,
+ * each rounded up to 256), filters it there and copies X back; the frame
+ * completes when its launch, and that copy, have ended (not on its own
+ * completion word), and only then does hasf_serve_wait return. The caller
+ * keeps the buffers alive and X untouched until then. The copies are
+ * asynchronous only from page-locked memory (hipHostMalloc, pinned tensors);
+ * from pageable memory they may hold up the dispatcher while they run.
+ * Validation and errors as hasf_serve_submit. */
+hasf_status hasf_serve_submit_host(hasf_server* s, const hasf_image* img, uint64_t* ticket);
 /* Wait until the frame completes (timeout_ms < 0: forever); HASF_ETIMEDOUT if
  * it has not completed in time (the frame stays queued). A ticket can be
  * waited for once; out may be NULL. */

@@ -100,7 +100,10 @@ struct Pool {
 
 struct Frame {
     uint64_t ticket = 0;
-    hasf_image img{};
+    hasf_image img{};   // as the kernel reads it (device pointers)
+    hasf_image himg{};  // a host frame: the caller's host buffers
+    bool host = false;  // copied to pool memory before its launch and back after it
+    size_t stage_bytes = 0;  // host frames: X, C and D packed (pitch W) after the scratch
     ImageLayout lay{};
     double cost = 0;
     bool grid = false;  // filtered by a grid of workgroups, alone in its launch
@@ -126,6 +129,12 @@ struct Lane {
 
 // offset of the descriptor after a GridCtl in a lane's meta block
 constexpr size_t GRID_DESC_OFF = (sizeof(GridCtl) + 255) / 256 * 256;
+
+// pool bytes of a frame: its scratch, then (host frames) its staged buffers
+size_t frame_bytes(const Frame* f)
+{
+    return f->lay.total() + f->stage_bytes;
+}
 
 double frame_cost(const hasf_image& im)
 {
@@ -173,7 +182,7 @@ void retire(hasf_server* s, Frame* f, double t, int status)
     f->t_done = t;
     f->status = status;
     f->done = true;
-    s->pool.release(f->off / 256, f->lay.total() / 256);
+    s->pool.release(f->off / 256, frame_bytes(f) / 256);
     --s->in_flight;
     if (status == HASF_OK) {
         ++s->completed;
@@ -201,6 +210,41 @@ void fill_desc(hasf_server* s, const Frame* f, ImgDesc& d)
     d.ent_msk = (uint64_t*)(base + f->lay.planes_bytes + f->lay.idx_bytes);
 }
 
+// A host frame's device copies, in its pool block after the scratch: X, C and
+// D at pitch W, each 256-byte aligned; img points there from its admission on.
+void stage_frame(hasf_server* s, Frame* f)
+{
+    char* p = s->pool_mem + f->off + f->lay.total();
+    const size_t plane = hasf_align256((size_t)f->himg.H * (size_t)f->himg.W);
+    f->img = f->himg;
+    f->img.ld = f->himg.W;
+    f->img.X = (uint8_t*)p;
+    f->img.C = f->himg.C ? (const uint8_t*)(p + plane) : nullptr;
+    f->img.D = f->himg.D ? (const uint8_t*)(p + (f->himg.C ? 2 : 1) * plane) : nullptr;
+}
+
+// the copies in before a launch and of X out after it, on the lane's stream
+hipError_t copy_in(const Frame* f, hipStream_t st)
+{
+    const hasf_image& h = f->himg;
+    hipError_t e = hipMemcpy2DAsync(f->img.X, (size_t)h.W, h.X, (size_t)h.ld, (size_t)h.W, (size_t)h.H,
+                                    hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && h.C)
+        e = hipMemcpy2DAsync((void*)f->img.C, (size_t)h.W, h.C, (size_t)h.ld, (size_t)h.W, (size_t)h.H,
+                             hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && h.D)
+        e = hipMemcpy2DAsync((void*)f->img.D, (size_t)h.W, h.D, (size_t)h.ld, (size_t)h.W, (size_t)h.H,
+                             hipMemcpyHostToDevice, st);
+    return e;
+}
+
+hipError_t copy_out(const Frame* f, hipStream_t st)
+{
+    const hasf_image& h = f->himg;
+    return hipMemcpy2DAsync(h.X, (size_t)h.ld, f->img.X, (size_t)h.W, (size_t)h.W, (size_t)h.H,
+                            hipMemcpyDeviceToHost, st);
+}
+
 void launch_failed(hasf_server* s, hipError_t e)
 {
     (void)hipGetLastError();
@@ -213,10 +257,12 @@ bool launch_grid_frame(hasf_server* s, Lane& ln)
 {
     Frame* f = s->pending.front();
     size_t off = 0;
-    if (!s->pool.alloc(f->lay.total() / 256, &off))
+    if (!s->pool.alloc(frame_bytes(f) / 256, &off))
         return false;
     f->off = off * 256;
     s->pending.pop_front();
+    if (f->host)
+        stage_frame(s, f);
     std::memset(ln.h_meta, 0, GRID_DESC_OFF);  // the GridCtl starts at 0
     fill_desc(s, f, *(ImgDesc*)(ln.h_meta + GRID_DESC_OFF));
     ln.h_done[0] = 0;  // not written by the grid kernel; the frame completes with its launch
@@ -229,10 +275,13 @@ bool launch_grid_frame(hasf_server* s, Lane& ln)
     s->batch_max = std::max(s->batch_max, 1);
     const int nwd = f->img.H * ((f->img.W + 63) / 64);
     const int grid = grid_blocks(nwd, s->ctx->num_cu * grid_occupancy() / 2);
-    hipError_t e = hipMemcpyAsync(ln.d_meta, ln.h_meta, GRID_DESC_OFF + sizeof(ImgDesc), hipMemcpyHostToDevice,
-                                  ln.stream);
+    hipError_t e = f->host ? copy_in(f, ln.stream) : hipSuccess;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ln.d_meta, ln.h_meta, GRID_DESC_OFF + sizeof(ImgDesc), hipMemcpyHostToDevice, ln.stream);
     if (e == hipSuccess)
         e = launch_grid((const ImgDesc*)(ln.d_meta + GRID_DESC_OFF), (GridCtl*)ln.d_meta, nullptr, grid, ln.stream);
+    if (e == hipSuccess && f->host)
+        e = copy_out(f, ln.stream);
     if (e == hipSuccess)
         e = hipEventRecord(ln.ev, ln.stream);
     if (e != hipSuccess)
@@ -266,7 +315,7 @@ bool launch_lane(hasf_server* s, Lane& ln)
                 continue;
             }
             size_t off = 0;
-            if (!s->pool.alloc(f->lay.total() / 256, &off))
+            if (!s->pool.alloc(frame_bytes(f) / 256, &off))
                 break;  // HBM footprint: wait until frames on the device finish
             f->off = off * 256;
             it = s->pending.erase(it);
@@ -279,7 +328,7 @@ bool launch_lane(hasf_server* s, Lane& ln)
             if (f->grid || (s->express && is_small(s, f) != small))
                 break;  // alone, or another class: the next free lane takes it
             size_t off = 0;
-            if (!s->pool.alloc(f->lay.total() / 256, &off))
+            if (!s->pool.alloc(frame_bytes(f) / 256, &off))
                 break;  // HBM footprint: wait until frames on the device finish
             f->off = off * 256;
             s->pending.pop_front();
@@ -293,7 +342,12 @@ bool launch_lane(hasf_server* s, Lane& ln)
     const int n = (int)take.size();
     ImgDesc* desc = (ImgDesc*)(ln.h_meta + 256);
     size_t lds_need = 0;
+    bool any_host = false;
     for (int q = 0; q < n; ++q) {
+        if (take[q]->host) {
+            stage_frame(s, take[q]);
+            any_host = true;
+        }
         fill_desc(s, take[q], desc[q]);
         lds_need = std::max(lds_need, take[q]->lay.lds_bytes);
         ln.h_done[q] = 0;
@@ -314,11 +368,21 @@ bool launch_lane(hasf_server* s, Lane& ln)
     const int grid = std::min(n, s->ctx->num_cu * occ);
     // h_meta is pinned and not rewritten before this lane's launch has ended,
     // so the copy may run after this call returns
-    hipError_t e = hipMemcpyAsync(ln.d_meta, ln.h_meta, 256 + sizeof(ImgDesc) * (size_t)n, hipMemcpyHostToDevice,
-                                  ln.stream);
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < n && e == hipSuccess && any_host; ++q)
+        if (take[q]->host)
+            e = copy_in(take[q], ln.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ln.d_meta, ln.h_meta, 256 + sizeof(ImgDesc) * (size_t)n, hipMemcpyHostToDevice,
+                           ln.stream);
     if (e == hipSuccess)
         e = launch_filter((const ImgDesc*)(ln.d_meta + 256), n, (int*)ln.d_meta, grid, block, lds_need,
                           ln.stream, ln.d_done);
+    // host frames: their results go back after the launch and they complete
+    // with it (their completion words only say that the kernel is done)
+    for (int q = 0; q < n && e == hipSuccess && any_host; ++q)
+        if (take[q]->host)
+            e = copy_out(take[q], ln.stream);
     if (e == hipSuccess)
         e = hipEventRecord(ln.ev, ln.stream);
     if (e != hipSuccess)
@@ -339,7 +403,7 @@ void serve_loop(hasf_server* s)
             const double t = now_s();
             for (size_t q = 0; q < ln.frames.size() && !ln.grid; ++q) {
                 Frame* f = ln.frames[q];
-                if (f && __atomic_load_n(ln.h_done + q, __ATOMIC_ACQUIRE)) {
+                if (f && !f->host && __atomic_load_n(ln.h_done + q, __ATOMIC_ACQUIRE)) {
                     retire(s, f, t, HASF_OK);
                     ln.frames[q] = nullptr;
                     progress = true;
@@ -528,7 +592,9 @@ hasf_status hasf_serve(hasf_ctx* ctx, const hasf_serve_opts* opts, hasf_server**
     return HASF_OK;
 }
 
-hasf_status hasf_serve_submit(hasf_server* s, const hasf_image* img, uint64_t* ticket)
+namespace {
+
+hasf_status submit(hasf_server* s, const hasf_image* img, uint64_t* ticket, bool host)
 {
     if (!s || !img || !ticket)
         return HASF_EINVAL;
@@ -543,6 +609,11 @@ hasf_status hasf_serve_submit(hasf_server* s, const hasf_image* img, uint64_t* t
     if (!f)
         return HASF_ENOMEM;
     f->img = *img;
+    if (host) {
+        f->host = true;
+        f->himg = *img;
+        f->stage_bytes = hasf_align256((size_t)img->H * (size_t)img->W) * (1 + (img->C ? 1 : 0) + (img->D ? 1 : 0));
+    }
     f->grid = (size_t)img->H * (size_t)img->W >= s->ctx->batch_grid_min_px;
     f->lay = image_layout(img->H, img->W, img->r, f->grid ? 0 : s->lds_cap);
     f->cost = frame_cost(*img);
@@ -552,7 +623,7 @@ hasf_status hasf_serve_submit(hasf_server* s, const hasf_image* img, uint64_t* t
             delete f;
             return s->fatal != HASF_OK ? (hasf_status)s->fatal : HASF_EINVAL;
         }
-        if (f->lay.total() > s->pool.size * 256) {
+        if (frame_bytes(f) > s->pool.size * 256) {
             ++s->rejected;
             delete f;
             return HASF_ENOMEM;  // could never be admitted
@@ -572,6 +643,18 @@ hasf_status hasf_serve_submit(hasf_server* s, const hasf_image* img, uint64_t* t
     }
     s->cv_work.notify_one();
     return HASF_OK;
+}
+
+}  // namespace
+
+hasf_status hasf_serve_submit(hasf_server* s, const hasf_image* img, uint64_t* ticket)
+{
+    return submit(s, img, ticket, false);
+}
+
+hasf_status hasf_serve_submit_host(hasf_server* s, const hasf_image* img, uint64_t* ticket)
+{
+    return submit(s, img, ticket, true);
 }
 
 hasf_status hasf_serve_wait(hasf_server* s, uint64_t ticket, int timeout_ms, hasf_result* out)

@@ -101,10 +101,12 @@ class _Stats(ctypes.Structure):
 _vp = ctypes.c_void_p
 _lib.hasf_serve.argtypes = [_vp, ctypes.POINTER(_ServeOpts), ctypes.POINTER(_vp)]
 _lib.hasf_serve_submit.argtypes = [_vp, ctypes.POINTER(_Image), ctypes.POINTER(ctypes.c_uint64)]
+_lib.hasf_serve_submit_host.argtypes = [_vp, ctypes.POINTER(_Image), ctypes.POINTER(ctypes.c_uint64)]
 _lib.hasf_serve_wait.argtypes = [_vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(_Result)]
 _lib.hasf_serve_stats.argtypes = [_vp, ctypes.POINTER(_Stats)]
 _lib.hasf_serve_stop.argtypes = [_vp]
-for _f in ("hasf_serve", "hasf_serve_submit", "hasf_serve_wait", "hasf_serve_stats", "hasf_serve_stop"):
+for _f in ("hasf_serve", "hasf_serve_submit", "hasf_serve_submit_host", "hasf_serve_wait", "hasf_serve_stats",
+           "hasf_serve_stop"):
     getattr(_lib, _f).restype = ctypes.c_int
 _lib.hasf_create.argtypes = [ctypes.POINTER(_Opts), ctypes.POINTER(_vp)]
 _lib.hasf_destroy.argtypes = [_vp]
@@ -410,7 +412,8 @@ class Context:
 
 class Server:
     """Served stream on a context's device (hasf_serve). Frames are device
-    tensors filtered in place; keep them alive until wait() returns."""
+    tensors filtered in place (submit_host: host tensors, copied in and out);
+    keep them alive until wait() returns."""
 
     def __init__(self, ctx: Context, pool_bytes: int = 0, lanes: int = 0, max_batch: int = 0,
                  max_pending: int = 0, persistent: bool = False, express_lanes: int = -1,
@@ -433,6 +436,30 @@ class Server:
         if st != HASF_OK:
             if check:
                 raise HasfError(st, "hasf_serve_submit")
+            return st
+        self._keep[t.value] = (X, C, D)
+        return t.value
+
+    def submit_host(self, X, C=None, r: int = 1, check: bool = True, D=None, conn: int = 0, order: int = 0):
+        """Queue a frame in host memory (hasf_serve_submit_host): X, C, D are 2D
+        uint8 CPU tensors with unit column stride and one pitch (pinned memory
+        keeps the copies asynchronous); X receives the result. Returns the
+        ticket (or the status when check=False and it fails)."""
+        for name, T in (("X", X), ("C", C), ("D", D)):
+            if T is None and name != "X":
+                continue
+            if (T is None or T.dtype != torch.uint8 or T.dim() != 2 or T.stride(1) != 1 or T.is_cuda
+                    or (T.shape[0] > 1 and T.stride(0) < T.shape[1])):
+                raise ValueError("%s must be a 2D uint8 CPU tensor with unit column stride" % name)
+            if name != "X" and (T.shape != X.shape or T.stride(0) != X.stride(0)):
+                raise ValueError("%s must have X's shape and pitch" % name)
+        im = _Image(X.data_ptr(), C.data_ptr() if C is not None else None, X.shape[0], X.shape[1], X.stride(0), r,
+                    D.data_ptr() if D is not None else None, conn, order)
+        t = ctypes.c_uint64()
+        st = _lib.hasf_serve_submit_host(self._h, ctypes.byref(im), ctypes.byref(t))
+        if st != HASF_OK:
+            if check:
+                raise HasfError(st, "hasf_serve_submit_host")
             return st
         self._keep[t.value] = (X, C, D)
         return t.value

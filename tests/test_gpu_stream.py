@@ -3,6 +3,7 @@ same in the mix as alone (hasf_filter on that frame) and as the oracle; also
 when admission is throttled by a tiny memory pool, with an invalid frame in the
 middle, with a full queue, and with frames of very different sizes, where a
 small frame finishes before a large one submitted with it."""
+import ctypes
 import time
 
 import numpy as np
@@ -237,4 +238,77 @@ def test_bad_express_options():
         assert e.value.status == hasf.HASF_EINVAL, kw
     # one lane: the default makes no express lane
     srv = hasf.Server(ctx(), lanes=1)
+    srv.stop()
+
+
+def _host(A, pinned):
+    t = torch.from_numpy(np.ascontiguousarray(A, dtype=np.uint8))
+    return t.pin_memory() if pinned else t.clone()
+
+
+def test_host_frames_equal_the_oracle():
+    # frames in host memory (hasf_serve_submit_host): copied into the pool,
+    # filtered and copied back; pinned and pageable buffers, with C and D,
+    # both pairs and orders, pitched rows, mixed with device frames in one
+    # stream, and a frame large enough for the grid path (launched alone)
+    c = hasf.Context(0, batch_grid_min_pixels=40000)
+    srv = hasf.Server(c, pool_bytes=256 << 20)
+    rng = np.random.default_rng(77)
+    items = []
+    for k in range(14):
+        H, W = (230, 260) if k == 5 else (int(rng.integers(20, 140)), int(rng.integers(20, 140)))
+        X = synth.disks_image(H, W, np.random.default_rng(7700 + k))
+        C = ((rng.random((H, W)) < 0.03) & (X != 0)).astype(np.uint8) if k % 3 == 0 else None
+        D = ((rng.random((H, W)) < 0.05) & (X == 0)).astype(np.uint8) if k % 4 == 1 else None
+        r, n, order = int(rng.integers(0, 6)), (4 if k % 5 == 2 else 8), k % 2
+        items.append((X, C, D, r, n, order))
+    say("host frames: 14, one on the grid path, mixed with device frames")
+    tickets, keep = [], []
+    for k, (X, C, D, r, n, order) in enumerate(items):
+        if k % 4 == 3:  # a device frame between the host frames
+            x = dev(X)
+            cd = dev(C) if C is not None else None
+            dd = dev(D) if D is not None else None
+            torch.cuda.synchronize()
+            tickets.append(srv.submit(x, cd, r, D=dd, conn=n, order=order))
+            keep.append(("dev", x))
+            continue
+        pinned = k % 2 == 0
+        if k == 6:  # pitched rows: a view into a wider buffer
+            buf = _host(np.zeros((X.shape[0], X.shape[1] + 13), np.uint8), pinned)
+            buf[:, :X.shape[1]] = torch.from_numpy(X)
+            xh = buf[:, :X.shape[1]]
+            ch = None if C is None else _host(np.pad(C, ((0, 0), (0, 13))), pinned)[:, :X.shape[1]]
+            dh = None if D is None else _host(np.pad(D, ((0, 0), (0, 13))), pinned)[:, :X.shape[1]]
+        else:
+            xh = _host(X, pinned)
+            ch = None if C is None else _host(C, pinned)
+            dh = None if D is None else _host(D, pinned)
+        tickets.append(srv.submit_host(xh, ch, r, D=dh, conn=n, order=order))
+        keep.append(("host", xh))
+    for t in tickets:
+        assert srv.wait(t, 60000) is not None
+    for k, ((X, C, D, r, n, order), (kind, buf)) in enumerate(zip(items, keep)):
+        got = host(buf) if kind == "dev" else buf.numpy().copy()
+        assert np.array_equal(got, oracle.hasf(X, C, r, D=D, n=n, order=order)), (k, kind)
+    srv.stop()
+
+
+def test_host_frame_arguments():
+    srv = hasf.Server(ctx(), pool_bytes=8 << 20)
+    X = torch.zeros((10, 12), dtype=torch.uint8)
+    with pytest.raises(ValueError):
+        srv.submit_host(X.cuda())  # a device tensor
+    with pytest.raises(ValueError):
+        srv.submit_host(X, C=torch.zeros((10, 11), dtype=torch.uint8))  # C of another shape
+    # through the C ABI: a NULL frame pointer and a bad radius are refused
+    lib = hasf.lib()
+    t = ctypes.c_uint64()
+    im = hasf._Image(None, None, 10, 12, 12, 1, None, 0, 0)
+    assert lib.hasf_serve_submit_host(srv._h, ctypes.byref(im), ctypes.byref(t)) == hasf.HASF_EINVAL
+    im = hasf._Image(X.data_ptr(), None, 10, 12, 12, hasf.HASF_R_MAX + 1, None, 0, 0)
+    assert lib.hasf_serve_submit_host(srv._h, ctypes.byref(im), ctypes.byref(t)) == hasf.HASF_EINVAL
+    # a frame whose staged buffers alone (16 MB) could never fit the 8 MB pool
+    big = torch.zeros((4000, 4000), dtype=torch.uint8)
+    assert srv.submit_host(big, None, 5, check=False) == hasf.HASF_ENOMEM
     srv.stop()
