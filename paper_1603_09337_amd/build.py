@@ -46,15 +46,21 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     objs = [os.path.join(objdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
     cmds = [[hipcc()] + HIPCC_FLAGS + inc + ["-c", "-o", o, os.path.join(CSRC, s)] for s, o in zip(SOURCES, objs)]
     jobs = jobs or min(len(cmds), max(1, min(16, os.cpu_count() or 1)))
-    with ThreadPoolExecutor(jobs) as ex:
-        for f in [ex.submit(_run, c, verbose) for c in cmds]:
-            f.result()
     tmp = OUT + ".tmp%d" % os.getpid()
-    _run([hipcc()] + HIPCC_FLAGS + ["-shared", "-o", tmp] + objs, verbose)
-    os.replace(tmp, OUT)
-    for o in objs:
-        os.remove(o)
-    os.rmdir(objdir)
+    try:
+        with ThreadPoolExecutor(jobs) as ex:
+            for f in [ex.submit(_run, c, verbose) for c in cmds]:
+                f.result()
+        _run([hipcc()] + HIPCC_FLAGS + ["-shared", "-o", tmp] + objs, verbose)
+        os.replace(tmp, OUT)
+    finally:
+        # the object folder (and a half-written library) go whether or not
+        # the build succeeded
+        for f in objs + [tmp]:
+            if os.path.exists(f):
+                os.remove(f)
+        if os.path.isdir(objdir):
+            os.rmdir(objdir)
     return OUT
 
 
