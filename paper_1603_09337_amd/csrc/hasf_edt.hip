@@ -26,8 +26,9 @@
 //                 too wide for a uint32 strip in LDS.
 //   edt_rows_env  the windowed search costs each pixel about its distance to
 //                 the nearest feature, so a strip whose column distances
-//                 average more than ENV_AVG is instead listed by edt_rows32
-//                 and done here, one row per workgroup, with Alg. 2's lower
+//                 average more than ENV_AVG and whose searches, sampled at
+//                 one pixel per thread, are long too is instead listed by
+//                 edt_rows32 and done here, one row per workgroup, with Alg. 2's lower
 //                 envelope built in parallel: the lower convex hull of the
 //                 points (k, k^2 + g(k)^2) per band of columns (a stack per
 //                 thread), the bands' hulls merged pairwise in log rounds
@@ -68,6 +69,13 @@ constexpr int CARRY_REG = 8;      // segments per thread kept in registers by ed
 // more than ENV_AVG: the windowed search costs a pixel about its distance.
 constexpr int ENV_AVG = 16;
 constexpr int ENV_CAP = 1024;
+// The column distances overstate the search where features are scattered
+// (a pixel's nearest feature is then much nearer than the nearest in its own
+// column), so a strip over ENV_AVG is listed only when a sample of its
+// searches (one pixel per thread, each stopped at SAMPLE_MAX columns and then
+// counted as ENV_CAP) averages more than SAMPLE_AVG columns.
+constexpr int SAMPLE_MAX = 64;
+constexpr int SAMPLE_AVG = 64;
 constexpr int ENV_NT = 256;       // threads of an edt_rows_env workgroup (one row at a time)
 constexpr int ENV_W_MAX = 16384;  // widest row edt_rows_env takes (its LDS: about 8 bytes per column)
 // an image with at most this many columns that hold a feature: edt_rows_env
@@ -388,6 +396,42 @@ __device__ __forceinline__ uint32_t row_min(const uint32_t* gr, int j, int W, in
     return best;
 }
 
+// Columns row_min would visit at one pixel of the strip (the distance at
+// which its search ends, to four columns), or ENV_CAP when that is
+// SAMPLE_MAX or more. Thread t of the first per * nr takes row t % nr and
+// column k * s + r mod W (k = t / nr, s = (W / per) | 1): an odd stride, so
+// the lanes of a wave read different LDS banks. Out of line: it runs only for strips the column
+// distances would list, and inlined it costs the strip kernel's common case.
+__device__ __attribute__((noinline)) uint32_t search_len(const uint32_t* g2s, int WP, int nr, int per, int W,
+                                                         int frame)
+{
+    const int t = (int)threadIdx.x;
+    if (t >= per * nr)
+        return 0;
+    const int r = t % nr, k = t / nr;
+    const int j = (int)(((long long)k * ((W / per) | 1) + r) % W);
+    const uint32_t* gr = g2s + r * WP + PAD;
+    uint32_t best = gr[j];
+    if (frame) {
+        const uint32_t e = (uint32_t)min(j + 1, W - j);
+        best = min(best, __umul24(e, e));
+    }
+    // four columns a side per step (the end is tested once per step, so
+    // the count is up to three columns long)
+    int d = 1;
+    for (; d < SAMPLE_MAX && (uint32_t)(d * d) < best; d += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t dd = (uint32_t)((d + u) * (d + u));
+            if (j - d - u >= 0)
+                best = min(best, __builtin_elementwise_add_sat(dd, gr[j - d - u]));
+            if (j + d + u < W)
+                best = min(best, __builtin_elementwise_add_sat(dd, gr[j + d + u]));
+        }
+    }
+    return (uint32_t)(d * d) < best ? (uint32_t)ENV_CAP : (uint32_t)d;
+}
+
 // edt_rows with g^2 as uint32 in LDS: each strip row holds PAD columns, the
 // W values, PAD columns. Without the frame the padding is G2_INF (it cannot
 // improve best); with the frame every column outside the window is a feature
@@ -400,9 +444,10 @@ __device__ __forceinline__ uint32_t row_min(const uint32_t* gr, int j, int W, in
 // and the strips of one segment read its masks and carries through one L2.
 //
 // hard_count / hard_list (may be NULL): a strip whose column distances
-// average more than ENV_AVG (each counted up to ENV_CAP) is appended to
-// hard_list and left to edt_rows_env (its windowed search would cost about
-// the distance per pixel).
+// average more than ENV_AVG (each counted up to ENV_CAP) and whose sampled
+// searches average more than SAMPLE_AVG columns is appended to hard_list and
+// left to edt_rows_env (its windowed search would cost about the distance
+// per pixel).
 template <int STRIP>
 __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restrict__ mask,
                                                          const int* __restrict__ above,
@@ -429,9 +474,11 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
         const int r = t / (2 * PAD), k = t - r * (2 * PAD);
         g2s[r * WP + (k < PAD ? k : W + k)] = pad;
     }
-    __shared__ uint32_t s_cost;
-    if (threadIdx.x == 0)
+    __shared__ uint32_t s_cost, s_len;
+    if (threadIdx.x == 0) {
         s_cost = 0;
+        s_len = 0;
+    }
     int has = 0;
     uint32_t cost = 0;
     // one column: its g^2 in the strip's rows (into LDS) and its cost
@@ -499,9 +546,20 @@ __global__ __launch_bounds__(ROWS_BLOCK) void edt_rows32(const uint32_t* __restr
             atomicAdd(&s_cost, cost);
         __syncthreads();
         if (s_cost > (uint32_t)ENV_AVG * (uint32_t)(nr * W)) {
-            if (threadIdx.x == 0)
-                hard_list[atomicAdd(hard_count, 1)] = strip_id;
-            return;
+            // thread t samples row t % nr at a column spread over the row
+            const int per = (int)blockDim.x / nr;
+            uint32_t len = search_len(g2s, WP, nr, per, W, frame);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1)
+                len += __shfl_xor(len, o);
+            if ((threadIdx.x & 63) == 0)
+                atomicAdd(&s_len, len);
+            __syncthreads();
+            if (s_len > (uint32_t)SAMPLE_AVG * (uint32_t)(per * nr)) {
+                if (threadIdx.x == 0)
+                    hard_list[atomicAdd(hard_count, 1)] = strip_id;
+                return;
+            }
         }
     }
 #pragma unroll

@@ -119,3 +119,27 @@ def test_edt_sparse_4096_parity_and_timing():
     # its pixels' distances, thousands of times the dense cost); the bound
     # leaves room for a busy device
     assert sparse < 4 * dense and sparse_f < 4 * dense
+
+
+@pytest.mark.parametrize("case", ["density 0.001", "2000 features, frame", "empty right quarter",
+                                  "empty band of 96 columns"])
+def test_edt_4096_scattered_features(case):
+    # scattered features: every column holds some, so the column distances
+    # are large while each pixel's nearest feature is near; a strip is then
+    # sampled, and its rows take the windowed search when the sample is
+    # short, else the envelope. An empty quarter or band of columns leaves
+    # some strips' samples long and others short.
+    rng = np.random.default_rng(9100)
+    frame = False
+    if case == "density 0.001":
+        F = (rng.random((4096, 4096)) < 0.001).astype(np.uint8)
+    elif case == "2000 features, frame":
+        F, frame = _sparse(4096, 4096, 2000, 9101), True
+    elif case == "empty right quarter":
+        F = (rng.random((4096, 4096)) < 0.005).astype(np.uint8)
+        F[:, 3072:] = 0
+    else:
+        F = (rng.random((4096, 4096)) < 0.005).astype(np.uint8)
+        F[:, 2000:2096] = 0
+    say("edt 4096^2 scattered:", case)
+    assert np.array_equal(_edt(F, frame), oracle.edt_sq(F, frame))
