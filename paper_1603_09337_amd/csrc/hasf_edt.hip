@@ -380,18 +380,25 @@ __device__ __forceinline__ uint32_t row_min(const uint32_t* gr, int j, int W, in
         }
         d = d0 + 4;
     }
-    // beyond the padding: checked, one column per side at a time
-    // (d, e < 2^16: 24-bit multiplies are exact)
+    // beyond the padding: with bounds checks (a uint32 strip row fits LDS
+    // only for W < 41000, so d + 3 and e stay below 2^16 and the 24-bit
+    // multiplies are exact)
     if (frame && __umul24(d, d) < best) {
         const uint32_t e = (uint32_t)min(j + 1, W - j);
         best = min(best, __umul24(e, e));
     }
-    for (; __umul24(d, d) < best && (j - d >= 0 || j + d < W); ++d) {
-        const uint32_t dd = __umul24(d, d);
-        if (j - d >= 0)
-            best = min(best, __builtin_elementwise_add_sat(dd, gr[j - d]));
-        if (j + d < W)
-            best = min(best, __builtin_elementwise_add_sat(dd, gr[j + d]));
+    // four columns a side per step, as within the padding (columns past the
+    // point where the search could stop are real candidates too, so they
+    // leave the minimum exact)
+    for (; __umul24(d, d) < best && (j - d >= 0 || j + d < W); d += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t dd = __umul24(d + u, d + u);
+            if (j - d - u >= 0)
+                best = min(best, __builtin_elementwise_add_sat(dd, gr[j - d - u]));
+            if (j + d + u < W)
+                best = min(best, __builtin_elementwise_add_sat(dd, gr[j + d + u]));
+        }
     }
     return best;
 }
